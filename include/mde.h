@@ -1,0 +1,263 @@
+/*
+ * mde.h -- C ABI of libmde.so: multi-determinant wave-function evaluation by
+ * the table method on one AMD MI355X (gfx950) GPU.
+ *
+ * Problem statement (Sec. II): for each walker R = (r_1..r_N) and spin
+ * sigma, the matrix M_sigma,k(i,j) = phi_j(r_i) (rows = electrons, columns =
+ * orbitals), and
+ *     Psi = sum_k alpha_k det M_up,k det M_dn,k            (Jastrow excluded)
+ * where every M_sigma,k is the reference matrix (orbitals 0..n-1) with some
+ * columns replaced by virtual orbitals n..n+m-1 (particle-hole excitations).
+ * Per single-electron move the library returns Psi(R')/Psi(R),
+ * grad_i ln Psi(R') and lap_i Psi(R')/Psi(R') (Sec. II quantities), using the
+ * table T = A0^-1 Phi (Sec. III), r x r determinants of table entries
+ * (Sec. III read-off, Algorithm 1 step 4), derivative tables (Sec. IV-A) and
+ * the Sherman-Morrison update of A0^-1 (Sec. III, SM eq.).
+ *
+ * Conventions
+ *  - Every function returns mde_status; MDE_OK is 0.  No exception crosses
+ *    the ABI.  On failure mde_error_string(ctx) holds a message.
+ *  - Arrays passed to init/propose/accept/eval/backward are DEVICE pointers
+ *    owned by the caller (for example torch tensors).  Setup calls
+ *    (mde_set_*) take HOST pointers and copy what they need.
+ *  - All device work is ordered on the hipStream_t given to mde_create
+ *    (NULL = the legacy default stream) and is asynchronous.  A context is
+ *    not thread-safe; use one context per stream.
+ *  - Internal state lives in a caller-allocated device workspace
+ *    (mde_workspace_bytes, mde_bind_workspace): the library itself calls no
+ *    device allocator after bind.
+ *  - Row-major layouts, walker index slowest.  An orbital block is
+ *    [5][n_orb]: component 0 = value, 1..3 = d/dx, d/dy, d/dz,
+ *    4 = laplacian.  Electrons are numbered 0..n_up-1 (spin up) then
+ *    n_up..n_up+n_dn-1 (spin down).  Orbitals 0..n_sigma-1 fill the reference
+ *    determinant of spin sigma; orbitals n_sigma..n_orb_sigma-1 are virtual.
+ *  - Excitation convention: an excitation is a list of (hole -> particle)
+ *    pairs, holes ascending and particles ascending, paired in that order;
+ *    the particle takes the hole's column.  Any other phase convention is
+ *    folded into the CI coefficient by the caller.
+ *  - Per-walker numerical problems do not fail a call: they set bits in a
+ *    caller-provided int32 status[W] (MDE_ST_* below).  Bits accumulate
+ *    (OR) until the caller clears the array.
+ */
+#ifndef MDE_H
+#define MDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MDE_OK = 0,
+    MDE_INVALID = 1,      /* bad argument (range, size, order of calls)      */
+    MDE_NOMEM = 2,        /* workspace too small / host allocation failed    */
+    MDE_DEVICE = 3,       /* a HIP runtime call failed                       */
+    MDE_STATE = 4,        /* call not valid in the current state             */
+    MDE_UNSUPPORTED = 5   /* size or mode outside what the library supports  */
+} mde_status;
+
+typedef enum {
+    MDE_FP64 = 0,         /* every step in FP64 (the reference form)          */
+    MDE_MIXED = 1         /* table GEMM and small determinants in FP32 (MFMA
+                             for the GEMM); LU, Sherman-Morrison denominators,
+                             CI coefficients and CI sums stay FP64            */
+} mde_precision;
+
+/* per-walker status bits */
+#define MDE_ST_SINGULAR_REF 1   /* zero pivot in the reference LU             */
+#define MDE_ST_SMALL_RATIO  2   /* |det A'/det A| below 1e-300 or not finite  */
+#define MDE_ST_NONFINITE    4   /* non-finite input or output                 */
+#define MDE_ST_ZERO_PSI     8   /* multi-determinant sum exactly zero / NaN   */
+
+/* Limits of this build. */
+#define MDE_MAX_ELEC  64        /* electrons per spin                         */
+#define MDE_MAX_VIRT  256       /* virtual orbitals per spin                  */
+#define MDE_MAX_ORDER 8         /* largest excitation order                   */
+
+typedef struct mde_ctx mde_ctx;
+typedef struct mde_group mde_group;
+typedef struct mde_graph mde_graph;
+
+typedef struct {
+    int32_t n_elec[2];      /* electrons per spin, 1..MDE_MAX_ELEC            */
+    int32_t n_orb[2];       /* orbitals per spin = n_elec + virtuals          */
+    int32_t max_walkers;    /* upper bound on W for this context              */
+    int32_t max_order;      /* largest excitation order, 1..MDE_MAX_ORDER     */
+    int32_t refresh_every;  /* recompute A0^-1 and T from scratch after this
+                               many accept calls (0 = never; default sweep)   */
+    int32_t precision;      /* mde_precision                                  */
+} mde_desc;
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Create a context for one wave function.  hip_stream: a hipStream_t (or
+ * NULL).  The context keeps host metadata only until mde_bind_workspace. */
+mde_status mde_create(const mde_desc *desc, void *hip_stream, mde_ctx **out);
+mde_status mde_destroy(mde_ctx *ctx);
+/* Last error message of ctx (static text if ctx is NULL); never NULL. */
+const char *mde_error_string(const mde_ctx *ctx);
+/* Library version string. */
+const char *mde_version(void);
+
+/* ---- the expansion (host pointers, copied) ----------------------------- */
+
+/* Unique excitations of one spin in CSR form (Sec. II particle-hole
+ * excitations; Sec. III table read-off).  Entry 0 must be the empty
+ * excitation (the reference).  holes[offsets[u]..offsets[u+1]) are hole
+ * indices in 0..n-1, ascending; particles[...] are orbital indices in
+ * n..n_orb-1, ascending.  Orders above desc.max_order, repeated or
+ * out-of-range indices give MDE_INVALID. */
+mde_status mde_set_excitations(mde_ctx *ctx, int32_t spin, int32_t n_exc,
+                               const int32_t *offsets, const int32_t *holes,
+                               const int32_t *particles);
+
+/* CI expansion (Sec. II Psi eq.): determinant I has coefficient coef[I] and
+ * uses up excitation up_idx[I] and down excitation dn_idx[I].  Indices refer
+ * to the lists given to mde_set_excitations (call that first). */
+mde_status mde_set_ci(mde_ctx *ctx, int64_t n_det, const double *coef,
+                      const int32_t *up_idx, const int32_t *dn_idx);
+
+/* ---- workspace --------------------------------------------------------- */
+
+/* Device bytes needed for W walkers (W <= max_walkers). */
+mde_status mde_workspace_bytes(const mde_ctx *ctx, int32_t W, size_t *bytes);
+/* Bind caller-owned device memory (256-byte aligned, >= the size above for
+ * the W passed there) and upload the expansion.  Synchronous. */
+mde_status mde_bind_workspace(mde_ctx *ctx, int32_t W, void *dev, size_t bytes);
+
+/* ---- evaluation (device pointers) -------------------------------------- */
+
+/* From-scratch start (Sec. III: inverse and determinants computed once):
+ * orb_up [W][n_up][5][n_orb_up], orb_dn [W][n_dn][5][n_orb_dn] hold every
+ * electron's orbital block at its current position.  Computes A0^-1 by LU
+ * with partial pivoting, T = A0^-1 Phi_V, all excited ratios and the CI sum.
+ * Outputs log|Psi| and sign(Psi) per walker ([W] each, may be NULL). */
+mde_status mde_init(mde_ctx *ctx, const double *orb_up, const double *orb_dn,
+                    double *log_abs_psi, double *sign_psi, int32_t *status);
+
+/* Recompute A0^-1, T and the sums from the orbital values the library keeps
+ * (no inputs needed).  Same outputs as mde_init. */
+mde_status mde_refresh(mde_ctx *ctx, double *log_abs_psi, double *sign_psi,
+                       int32_t *status);
+
+/* Proposal for electron e moving to r_e' (Algorithm 1; Sec. IV-A):
+ * new_orb [W][5][n_orb_sigma(e)] is that electron's orbital block at r_e'.
+ * Outputs ratio[W] = Psi(R')/Psi(R), grad[W][3] = grad_e ln Psi(R'),
+ * lap[W] = lap_e Psi(R')/Psi(R').  State is unchanged until mde_accept. */
+mde_status mde_propose(mde_ctx *ctx, int32_t e, const double *new_orb,
+                       double *ratio, double *grad, double *lap, int32_t *status);
+
+/* grad_e ln Psi(R) and lap_e Psi(R)/Psi(R) at the current position;
+ * cur_orb [W][5][n_orb] is electron e's block at r_e.  Replaces any pending
+ * proposal (accepting it afterwards changes nothing). */
+mde_status mde_grad_lap(mde_ctx *ctx, int32_t e, const double *cur_orb,
+                        double *grad, double *lap, int32_t *status);
+
+/* Commit the pending proposal of electron e for walkers with accept[w] != 0
+ * (uint8 [W]): Sherman-Morrison update of A0^-1 (Sec. III SM eq.), table,
+ * reference determinant and CI sum.  Every refresh_every calls the state is
+ * recomputed from scratch (mde_refresh without outputs). */
+mde_status mde_accept(mde_ctx *ctx, int32_t e, const uint8_t *accept);
+
+/* Copy internal state for checks.  what: 0 = A0^-1 of spin s [W][n][n],
+ * 1 = table T_V of spin s [W][n][m] (FP64; in MIXED mode converted from
+ * FP32), 2 = excited ratios D_u/D_0 of spin s [W][n_exc] in the caller's
+ * excitation order (current positions), 3 = log|det A0| of spin s [W],
+ * 4 = multi-determinant sum N = Psi / (D0_up D0_dn) [W].  dst is a device
+ * pointer of FP64. */
+mde_status mde_export(mde_ctx *ctx, int32_t what, int32_t spin, double *dst);
+
+/* ---- adjoint (new path; see the header of each call) ------------------- */
+
+/* Forward from explicit tables: N = sum_I coef[I] det S_up,I det S_dn,I with
+ * S[j][l] = T_sigma[h_j][p_l - n] (Sec. III r x r read-off).  T_up
+ * [W][n_up][m_up], T_dn [W][n_dn][m_dn], coef [n_det] (device, FP64).
+ * Outputs log|N| and sign(N) per walker.  Keeps what mde_backward needs. */
+mde_status mde_eval_tables(mde_ctx *ctx, const double *T_up, const double *T_dn,
+                           const double *coef, double *log_abs, double *sign,
+                           int32_t *status);
+
+/* Adjoint of the last mde_eval_tables: with go[W] the upstream gradient of
+ * log|N_w|, grad_coef[I] = sum_w go_w dlog|N_w|/dcoef_I (deterministic order)
+ * and grad_T_sigma[w] = go_w dlog|N_w|/dT_sigma[w] ([W][n][m]). */
+mde_status mde_backward(mde_ctx *ctx, const double *go, double *grad_coef,
+                        double *grad_T_up, double *grad_T_dn);
+
+/* ---- tuning -------------------------------------------------------------- */
+
+/* Work decomposition of the determinant kernel for one spin: walker tile
+ * (1..64, power of two), excitations per work item, threads per block
+ * (64..1024).  0 keeps the current value.  Takes effect at the next
+ * mde_init / mde_refresh (call mde_refresh after changing it). */
+mde_status mde_set_plan(mde_ctx *ctx, int32_t spin, int32_t walker_tile,
+                        int32_t item_exc, int32_t threads);
+mde_status mde_get_plan(const mde_ctx *ctx, int32_t spin, int32_t *walker_tile,
+                        int32_t *item_exc, int32_t *threads);
+
+/* Time candidate plans on this context's current state (after mde_init) with
+ * proposals of electron 0 and electron n_up (new_orb_up/new_orb_dn: device
+ * blocks [W][5][n_orb]); keep the fastest per spin.  If cache_path is not
+ * NULL the choice is read from / appended to that text file, keyed by the
+ * problem shape.  Restores the state (refresh) before returning. */
+mde_status mde_autotune(mde_ctx *ctx, const double *new_orb_up,
+                        const double *new_orb_dn, const char *cache_path);
+
+/* ---- graphs ------------------------------------------------------------- */
+
+/* Capture every call made on ctx's stream between begin and end into a HIP
+ * graph (no host synchronisation happens in the evaluation calls).  Replays
+ * repeat the captured calls with the same pointers; the caller refreshes the
+ * content of its input buffers between replays.  A sequence that ends with a
+ * refresh leaves the state consistent for replay. */
+mde_status mde_capture_begin(mde_ctx *ctx);
+mde_status mde_capture_end(mde_ctx *ctx, mde_graph **out);
+mde_status mde_graph_launch(mde_graph *g, void *hip_stream);
+mde_status mde_graph_destroy(mde_graph *g);
+
+/* ---- uneven batch ------------------------------------------------------- */
+
+/* Pack n bound contexts (same stream, same precision) so that one propose
+ * runs as one persistent launch of the determinant kernel over the work
+ * items of every instance (Sec. V: the tiny determinants are independent).
+ * All contexts are switched to one common walker tile; call mde_init (or
+ * mde_refresh) on each context after mde_group_create.  The group's tables
+ * live in caller-owned device memory of mde_group_workspace_bytes bytes. */
+mde_status mde_group_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *bytes);
+mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t bytes,
+                            mde_group **out);
+mde_status mde_group_destroy(mde_group *g);
+/* e[n] (host): moving electron per instance; new_orb[n], ratio[n], grad[n],
+ * lap[n], status[n] (host arrays of device pointers, per-instance layouts as
+ * in mde_propose). */
+mde_status mde_group_propose(mde_group *g, const int32_t *e,
+                             const double *const *new_orb, double *const *ratio,
+                             double *const *grad, double *const *lap,
+                             int32_t *const *status);
+/* accept[n] (host array of device uint8 [W_i] pointers). */
+mde_status mde_group_accept(mde_group *g, const int32_t *e,
+                            const uint8_t *const *accept);
+/* Last error message of a group call. */
+const char *mde_group_error_string(const mde_group *g);
+/* Capture / replay work on groups exactly as on contexts. */
+mde_status mde_group_capture_begin(mde_group *g);
+mde_status mde_group_capture_end(mde_group *g, mde_graph **out);
+
+/* ---- synthetic orbital provider (s-Gaussians) --------------------------- */
+
+/* Basis of nb unnormalised s-Gaussians chi_b(r) = exp(-expo_b |r - c_b|^2)
+ * and MO coefficients mo [n_orb][nb] for spin `spin` (host, copied).  Call
+ * before mde_workspace_bytes: the basis lives in the workspace. */
+mde_status mde_sgauss_set_basis(mde_ctx *ctx, int32_t spin, int32_t nb,
+                                const double *centres, const double *expo,
+                                const double *mo);
+/* Orbital blocks at positions pos [npos][3] (device) -> out [npos][5][n_orb]
+ * (device): value, gradient, laplacian of phi_p = sum_b mo[p][b] chi_b. */
+mde_status mde_sgauss_eval(mde_ctx *ctx, int32_t spin, int32_t npos,
+                           const double *pos, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDE_H */

@@ -142,7 +142,7 @@ def mds(sysm, orb_up: np.ndarray, orb_dn: np.ndarray, e_deriv: int = -1,
     ex_u, ex_d = sysm.exc
     coef = _f64(sysm.coef if coef is None else coef)
     sh = np.full(W, np.nan) if shift is None else _f64(np.broadcast_to(shift, (W,)))
-    out = np.empty((W, 10))
+    out = np.empty((W, 15))
     ru = np.empty((W, ex_u.n_exc)) if ratios else None
     rd = np.empty((W, ex_d.n_exc)) if ratios else None
     rc = lib().oracle_mds_batch(W, nu, nd, nou, nod, orb_up, orb_dn,
@@ -154,7 +154,8 @@ def mds(sysm, orb_up: np.ndarray, orb_dn: np.ndarray, e_deriv: int = -1,
     if rc != 0:
         raise RuntimeError("oracle_mds_batch failed")
     res = dict(shift=out[:, 0].copy(), psi=out[:, 1].copy(), dpsi=out[:, 2:6].copy(),
-               sign0=out[:, [6, 8]].copy(), log0=out[:, [7, 9]].copy())
+               sign0=out[:, [6, 8]].copy(), log0=out[:, [7, 9]].copy(),
+               psi_abs=out[:, 10].copy(), dpsi_abs=out[:, 11:15].copy())
     if ratios:
         res["ratio_up"], res["ratio_dn"] = ru, rd
     return res
@@ -181,7 +182,13 @@ def move(sysm, pos: np.ndarray, e: int, new_r: np.ndarray, coef=None):
     ratio = r1["psi"] / r0["psi"]
     grad = r1["dpsi"][:, :3] / r1["psi"][:, None]
     lap = r1["dpsi"][:, 3] / r1["psi"]
-    return dict(ratio=ratio, grad=grad, lap=lap, psi_old=r0, psi_new=r1)
+    # condition-aware scales of x = sum(a) / sum(b):
+    #   X = (sum|a| + |x| sum|b|) / |sum b|
+    sc_ratio = (r1["psi_abs"] + np.abs(ratio) * r0["psi_abs"]) / np.abs(r0["psi"])
+    sc_d = (r1["dpsi_abs"] + np.abs(r1["dpsi"] / r1["psi"][:, None]) * r1["psi_abs"][:, None]) \
+        / np.abs(r1["psi"])[:, None]
+    return dict(ratio=ratio, grad=grad, lap=lap, psi_old=r0, psi_new=r1,
+                scale_ratio=sc_ratio, scale_grad=sc_d[:, :3], scale_lap=sc_d[:, 3])
 
 
 def grad_lap(sysm, pos: np.ndarray, e: int, coef=None):

@@ -195,7 +195,9 @@ static void build_matrix(int n, int n_orb, const double *orb, const int *col,
 /* out[0] shift used, out[1] psi = sum_I c_I D_up D_dn exp(-shift),
  * out[2..5] the same sum with the moved electron's row replaced by
  * d/dx, d/dy, d/dz, laplacian (zero when e_deriv < 0),
- * out[6..9] sign and log|det| of the up and down reference determinants.
+ * out[6..9] sign and log|det| of the up and down reference determinants,
+ * out[10] sum of |terms| of out[1], out[11..14] sums of |terms| of
+ * out[2..5] (scales for condition-aware comparisons).
  * ratio_up[u] = D_u / D_0 for every up excitation (optional), same for down.
  */
 static int mds_walker(int n_up, int n_dn, int no_up, int no_dn,
@@ -244,21 +246,27 @@ static int mds_walker(int n_up, int n_dn, int no_up, int no_dn,
     if (isnan(shift)) shift = lg[0][0] + lg[1][0];
     out[0] = shift;
 
-    double psi = 0.0, dpsi[4] = {0, 0, 0, 0};
+    double psi = 0.0, dpsi[4] = {0, 0, 0, 0}, apsi = 0.0, adpsi[4] = {0, 0, 0, 0};
     for (int64_t I = 0; I < n_det; ++I) {
         int a = iu[I], b = id[I];
         double t = coef[I] * sg[0][a] * sg[1][b] * exp(lg[0][a] + lg[1][b] - shift);
         psi += t;
+        apsi += fabs(t);
         if (ds >= 0) {
             int ue = (ds == 0) ? a : b;   /* excitation of the moved spin */
             int uo = (ds == 0) ? b : a;
-            for (int k = 0; k < 4; ++k)
-                dpsi[k] += coef[I] * sga[4 * ue + k] * sg[1 - ds][uo] *
-                           exp(lga[4 * ue + k] + lg[1 - ds][uo] - shift);
+            for (int k = 0; k < 4; ++k) {
+                double td = coef[I] * sga[4 * ue + k] * sg[1 - ds][uo] *
+                            exp(lga[4 * ue + k] + lg[1 - ds][uo] - shift);
+                dpsi[k] += td;
+                adpsi[k] += fabs(td);
+            }
         }
     }
     out[1] = psi;
     for (int k = 0; k < 4; ++k) out[2 + k] = dpsi[k];
+    out[10] = apsi;
+    for (int k = 0; k < 4; ++k) out[11 + k] = adpsi[k];
 
     double *rat[2] = {ratio_up, ratio_dn};
     for (int s = 0; s < 2; ++s) {
@@ -273,7 +281,7 @@ static int mds_walker(int n_up, int n_dn, int no_up, int no_dn,
 
 /* Batched over W walkers (OpenMP over walkers).  Strides: orb_up walker
  * stride n_up*5*no_up etc.  shift[w] may be NaN (use the walker's own
- * reference log-determinants).  out is [W][10]; ratio_* are [W][nx_*] or NULL. */
+ * reference log-determinants).  out is [W][15]; ratio_* are [W][nx_*] or NULL. */
 int oracle_mds_batch(int W, int n_up, int n_dn, int no_up, int no_dn,
                      const double *orb_up, const double *orb_dn,
                      int nx_up, const int *off_up, const int *h_up, const int *p_up,
@@ -289,7 +297,7 @@ int oracle_mds_batch(int W, int n_up, int n_dn, int no_up, int no_dn,
         err |= mds_walker(n_up, n_dn, no_up, no_dn, orb_up + w * su, orb_dn + w * sd,
                           nx_up, off_up, h_up, p_up, nx_dn, off_dn, h_dn, p_dn,
                           n_det, coef, iu, id, e_deriv, shift ? shift[w] : NAN,
-                          out + (size_t)w * 10,
+                          out + (size_t)w * 15,
                           ratio_up ? ratio_up + (size_t)w * nx_up : NULL,
                           ratio_dn ? ratio_dn + (size_t)w * nx_dn : NULL);
     }

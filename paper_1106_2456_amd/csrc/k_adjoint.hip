@@ -1,0 +1,163 @@
+// Adjoint of the multi-determinant sum written in table form,
+//   N = sum_I c_I det S_up,I det S_dn,I,  S[j][l] = T[h_j][p_l]  (Sec. III).
+//   dlog|N|/dc_I            = det S_up,I det S_dn,I / N
+//   dlog|N|/dT_sigma[h][p]  = sum over excitations u of sigma holding hole h
+//                             at position j and particle p at position l of
+//                             C_u cof(S_u)[j][l] / N,
+// with C_u the CI weight of u (sum of c_I det S_other over the terms using
+// u) and cof(S)[j][l] = d det S / d S[j][l].  The table-entry gradient is
+// gathered through an inverted index (entry -> (u, j, l)), so every output
+// element is one fixed-order sum: no atomics, bitwise-reproducible.
+#include "mde_internal.h"
+#include "smalldet.h"
+
+namespace mde {
+
+__device__ __forceinline__ int exc_byte_a(const uint4 &x, int i) {
+    uint32_t word = (i >> 2) == 0 ? x.x : (i >> 2) == 1 ? x.y : (i >> 2) == 2 ? x.z : x.w;
+    return (int)((word >> ((i & 3) * 8)) & 0xffu);
+}
+
+__global__ void k_gw(const InstDev *__restrict__ insts, const double *__restrict__ go) {
+    const InstDev &I = insts[0];
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < I.W) I.Lnew[w] = go[w] / I.Nold[w];
+}
+
+// grad_c[I] = sum_w gw[w] R_up[w][u(I)] R_dn[w][d(I)]; one wave per up
+// excitation u, lanes over walkers, fixed butterfly reduction.
+__global__ void k_grad_coef(const InstDev *__restrict__ insts, double *__restrict__ grad_coef) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[0];
+    const SpinDev &O = I.s[1];
+    const int lane = threadIdx.x & 63;
+    const int u = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (u >= S.U) return;
+    const int a = S.ci_seg[u], b = S.ci_seg[u + 1];
+    const int WT = S.WT, W = I.W;
+    for (int k = a; k < b; ++k) {
+        const int d = S.ci_other[k];
+        double s = 0.0;
+        for (int w0 = 0; w0 < W; w0 += 64) {
+            const int w = w0 + lane;
+            if (w < W) {
+                const int t = w / WT, wl = w - t * WT;
+                const double ru = S.R[((size_t)t * S.U + u) * WT + wl];
+                const double rd = O.R[((size_t)t * O.U + d) * WT + wl];
+                s = fma(I.Lnew[w] * ru, rd, s);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) grad_coef[S.ci_idx[k]] = s;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ double cof_entry(const double *tabs, const uint4 &ex, int m, int WTP,
+                                            int wl, int j, int l) {
+    double col[K][K], c[K], y[K];
+#pragma unroll
+    for (int jj = 0; jj < K; ++jj) {
+        const int p = exc_byte_a(ex, 8 + jj);
+#pragma unroll
+        for (int r = 0; r < K; ++r) col[jj][r] = tabs[(exc_byte_a(ex, r) * m + p) * WTP + wl];
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) c[r] = (r == j) ? 1.0 : 0.0;
+    (void)SmallDet<K, double>::run(col, c, y);
+    // y[l] = det(S with column l -> e_j) = cof(S)[j][l]
+    double out = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < K; ++jj) out = (jj == l) ? y[jj] : out;
+    return out;
+}
+
+__device__ double cof_entry_generic(const double *tabs, const uint4 &ex, int k, int m, int WTP,
+                                    int wl, int j, int l) {
+    double col[8][8], c[8], y[8];
+    for (int jj = 0; jj < k; ++jj) {
+        const int p = exc_byte_a(ex, 8 + jj);
+        for (int r = 0; r < k; ++r) col[jj][r] = tabs[(exc_byte_a(ex, r) * m + p) * WTP + wl];
+    }
+    for (int r = 0; r < k; ++r) c[r] = (r == j) ? 1.0 : 0.0;
+    (void)small_det_generic<double>(k, col, c, y);
+    return y[l];
+}
+
+// grad_T_sigma: one block per walker tile; the tile's table in LDS; lanes
+// (slot, walker) walk table entries and their inverted lists.
+__global__ void __launch_bounds__(1024)
+k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__ Tin,
+         double *__restrict__ grad_T) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[spin];
+    const int n = S.n, m = S.m, WT = S.WT, WTP = S.WTP, W = I.W;
+    const int t = blockIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int wl = tid % WT, slot = tid / WT, nslot = nthr / WT;
+    extern __shared__ double tabs[];
+    const int nm = n * m;
+    for (int idx = tid; idx < nm * WT; idx += nthr) {
+        const int e = idx % nm, l = idx / nm, w = t * WT + l;
+        tabs[e * WTP + l] = (w < W) ? Tin[(size_t)w * nm + e] : 0.0;
+    }
+    __syncthreads();
+    const int w = t * WT + wl;
+    const double gw = (w < W) ? I.Lnew[w] : 0.0;
+    const double *__restrict__ Cb = S.C + (size_t)t * S.U * WT;
+    for (int e = slot; e < nm; e += nslot) {
+        const int a = S.inv_off[e], b = S.inv_off[e + 1];
+        double acc = 0.0;
+        for (int q = a; q < b; ++q) {
+            const int code = S.inv_ent[q];
+            const int u = code >> 10, k = (code >> 6) & 15, j = (code >> 3) & 7, l = code & 7;
+            const uint4 ex = S.ex[u];
+            double cf;
+            switch (k) {
+                case 1: cf = 1.0; break;
+                case 2: cf = cof_entry<2>(tabs, ex, m, WTP, wl, j, l); break;
+                case 3: cf = cof_entry<3>(tabs, ex, m, WTP, wl, j, l); break;
+                case 4: cf = cof_entry<4>(tabs, ex, m, WTP, wl, j, l); break;
+                default: cf = cof_entry_generic(tabs, ex, k, m, WTP, wl, j, l); break;
+            }
+            acc = fma(Cb[(size_t)u * WT + wl], cf, acc);
+        }
+        if (w < W) grad_T[(size_t)w * nm + e] = gw * acc;
+    }
+}
+
+hipError_t launch_backward(hipStream_t st, const InstDev *d_inst, const InstDev &h,
+                           const double *go, const double *Nw, const double *coef,
+                           double *grad_coef, double *grad_T_up, double *grad_T_dn,
+                           const double *T_up, const double *T_dn) {
+    (void)Nw; (void)coef;
+    hipLaunchKernelGGL(k_gw, dim3((h.W + 255) / 256), dim3(256), 0, st, d_inst, go);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (grad_coef) {
+        const int wpb = 4;
+        hipLaunchKernelGGL(k_grad_coef, dim3((h.s[0].U + wpb - 1) / wpb), dim3(64 * wpb), 0, st,
+                           d_inst, grad_coef);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const double *Tin[2] = {T_up, T_dn};
+    double *gT[2] = {grad_T_up, grad_T_dn};
+    for (int s = 0; s < 2; ++s) {
+        if (!gT[s]) continue;
+        const SpinDev &S = h.s[s];
+        const size_t lds = sizeof(double) * (size_t)S.n * S.m * S.WTP;
+        const int threads = S.WT >= 64 ? 1024 : 256;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_grad_T,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles), dim3(threads), lds, st, d_inst, s, Tin[s],
+                           gT[s]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace mde

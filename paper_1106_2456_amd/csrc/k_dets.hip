@@ -1,0 +1,567 @@
+// Determinant-stage kernels: the persistent gather + small-determinant + CI
+// kernel (Sec. III read-off, Algorithm 1 step 4, Sec. IV-A derivative terms),
+// the CI precontraction, the per-walker finish, and the N sums.
+//
+// Data layout on chip (LDS), walker fastest: entry e of the table for
+// walker-lane wl sits at tab[e * WTP + wl].  With a walker tile of 64 the 64
+// lanes of a wave are 64 walkers working on the same excitation: the
+// excitation's indices are wave-uniform and every LDS gather is a
+// conflict-free 512-byte row.  With small tiles (large n) the lanes of a wave
+// take different excitations of the same walker(s).
+#include "mde_internal.h"
+#include "smalldet.h"
+
+namespace mde {
+
+// Excitation record: bytes 0..7 holes, bytes 8..15 local particle indices.
+__device__ __forceinline__ int exc_byte(const uint4 &x, int i) {
+    const uint32_t word = (i >> 2) == 0 ? x.x : (i >> 2) == 1 ? x.y : (i >> 2) == 2 ? x.z : x.w;
+    return (int)((word >> ((i & 3) * 8)) & 0xffu);
+}
+
+// ---------------------------------------------------------------------------
+// persistent determinant kernel
+// ---------------------------------------------------------------------------
+
+// One order-K excitation for walker-lane wl.  PROPOSE: accumulate
+// C_u * (R_u, G^x_u, G^y_u, G^z_u, G^L_u) with
+//   R_u = det S,  G^a_u = rho^a R_u + sum_j g^a[p_j] y_j,  y = adj(S) c'[h].
+// VALUES: return det S.
+template <int K, typename TT, int MODE>
+__device__ __forceinline__ double det_one(const uint4 &ex, const TT *__restrict__ tabs,
+                                          const TT *__restrict__ gs, const TT *__restrict__ cs,
+                                          int m, int WTP, int wl, const double rhoA[4],
+                                          double Cu, double acc[NSUM]) {
+    int h[K], hm[K], p[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        h[j] = exc_byte(ex, j);
+        hm[j] = h[j] * m;
+        p[j] = exc_byte(ex, 8 + j);
+    }
+    TT col[K][K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int r = 0; r < K; ++r) col[j][r] = tabs[(hm[r] + p[j]) * WTP + wl];
+    TT c[K], y[K];
+    if (MODE == DM_VALUES) {
+#pragma unroll
+        for (int r = 0; r < K; ++r) c[r] = TT(0);
+        return (double)SmallDet<K, TT>::run(col, c, y);
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) c[r] = cs[h[r] * WTP + wl];
+    const TT det = SmallDet<K, TT>::run(col, c, y);
+    const double dd = (double)det;
+    acc[0] = fma(Cu, dd, acc[0]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        TT s = TT(0);
+#pragma unroll
+        for (int j = 0; j < K; ++j) s = fma(gs[(a * m + p[j]) * WTP + wl], y[j], s);
+        const double G = fma(rhoA[a], dd, (double)s);
+        acc[1 + a] = fma(Cu, G, acc[1 + a]);
+    }
+    return dd;
+}
+
+template <typename TT, int MODE>
+__device__ double det_one_generic(int k, const uint4 &ex, const TT *__restrict__ tabs,
+                                  const TT *__restrict__ gs, const TT *__restrict__ cs, int m,
+                                  int WTP, int wl, const double rhoA[4], double Cu,
+                                  double acc[NSUM]) {
+    int h[MAXK], p[MAXK];
+    for (int j = 0; j < k; ++j) {
+        h[j] = exc_byte(ex, j);
+        p[j] = exc_byte(ex, 8 + j);
+    }
+    TT col[8][8], c[8], y[8];
+    for (int j = 0; j < k; ++j)
+        for (int r = 0; r < k; ++r) col[j][r] = tabs[(h[r] * m + p[j]) * WTP + wl];
+    for (int r = 0; r < k; ++r) c[r] = (MODE == DM_VALUES) ? TT(0) : cs[h[r] * WTP + wl];
+    const TT det = small_det_generic<TT>(k, col, c, y);
+    const double dd = (double)det;
+    if (MODE == DM_VALUES) return dd;
+    acc[0] = fma(Cu, dd, acc[0]);
+    for (int a = 0; a < 4; ++a) {
+        TT s = TT(0);
+        for (int j = 0; j < k; ++j) s = fma(gs[(a * m + p[j]) * WTP + wl], y[j], s);
+        const double G = fma(rhoA[a], dd, (double)s);
+        acc[1 + a] = fma(Cu, G, acc[1 + a]);
+    }
+    return dd;
+}
+
+// Loop over the item's excitations; the CI weight of the next excitation is
+// loaded while the current one is evaluated.
+template <int K, typename TT, int MODE, int WT>
+__device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
+                                         const uint4 *__restrict__ exl, const TT *tabs,
+                                         const TT *gs, const TT *cs, int wl, int slot, int nslot,
+                                         const double rhoA[4], double acc[NSUM]) {
+    const int len = it.u1 - it.u0;
+    const size_t base = ((size_t)it.tile * S.U + it.u0) * WT;
+    const auto Cb = MDE_G(double, S.C) + base;
+    const auto Rb = MDE_GW(double, S.R) + base;
+    const int m = S.m, WTP = S.WTP;
+    int j = slot;
+    if (WT == 64) j = __builtin_amdgcn_readfirstlane(j);
+    double Cn = 0.0;
+    if (MODE == DM_PROPOSE && j < len) Cn = Cb[(size_t)j * WT + wl];
+    for (; j < len; j += nslot) {
+        uint4 ex = exl[j];
+        if (WT == 64) {
+            // one excitation per wave: keep its indices (and all gather
+            // address arithmetic) in scalar registers
+            ex.x = __builtin_amdgcn_readfirstlane(ex.x);
+            ex.y = __builtin_amdgcn_readfirstlane(ex.y);
+            ex.z = __builtin_amdgcn_readfirstlane(ex.z);
+            ex.w = __builtin_amdgcn_readfirstlane(ex.w);
+        }
+        const double Cu = Cn;
+        if (MODE == DM_PROPOSE && j + nslot < len) Cn = Cb[(size_t)(j + nslot) * WT + wl];
+        double R;
+        if (K > 0)
+            R = det_one<(K > 0 ? K : 1), TT, MODE>(ex, tabs, gs, cs, m, WTP, wl, rhoA, Cu, acc);
+        else
+            R = det_one_generic<TT, MODE>(it.order, ex, tabs, gs, cs, m, WTP, wl, rhoA, Cu, acc);
+        if (MODE == DM_VALUES) Rb[(size_t)j * WT + wl] = R;
+    }
+}
+
+template <typename TT, int MODE, int WT>
+__global__ void __launch_bounds__(1024)
+k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int n_items,
+      int ex_cap, const MoveArgs *__restrict__ moves, MoveArgs m1, int32_t *__restrict__ counter,
+      const double *tab0, const double *tab1) {
+    extern __shared__ uint4 smem4[];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int wl = tid % WT;
+    const int slot = tid / WT;
+    const int nslot = nthr / WT;
+    uint4 *exl = smem4;
+    unsigned char *tab_raw = reinterpret_cast<unsigned char *>(smem4 + ex_cap);
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&counter[0], 1);
+        __syncthreads();
+        const int gi = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (gi >= n_items) break;
+        const WorkItem it = items[gi];
+        const InstDev &I = insts[it.inst];
+        const SpinDev &S = I.s[it.spin];
+        if (MODE == DM_PROPOSE) {
+            const int mspin = moves ? moves[it.inst].spin : m1.spin;
+            if (mspin != it.spin) continue;
+        }
+        const int n = S.n, m = S.m, WTP = S.WTP, W = I.W;
+        TT *tabs = reinterpret_cast<TT *>(tab_raw);
+        TT *gs = tabs + n * m * WTP;
+        TT *cs = gs + 4 * m * WTP;
+        const int w0 = it.tile * WT;
+        const int nm = n * m;
+        // ---- stage the excitation records and the walker tile's tables ----
+        {
+            // records as 4 x 32-bit words (global loads)
+            const auto exg = MDE_G(uint32_t, S.ex) + (size_t)it.u0 * 4;
+            uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
+            for (int idx = tid; idx < (it.u1 - it.u0) * 4; idx += nthr) exw[idx] = exg[idx];
+        }
+        // proposal tables are stored walker-tiled ([tile][e][WT]): a straight
+        // copy into the padded LDS rows, no index division
+        if (MODE == DM_PROPOSE) {
+            const size_t tn = (size_t)it.tile * nm * WT, tg = (size_t)it.tile * 4 * m * WT,
+                         tc = (size_t)it.tile * n * WT;
+            if (sizeof(TT) == 8) {
+                const auto Tg = MDE_G(double, I.Tp) + tn;
+                const auto gg = MDE_G(double, I.g) + tg;
+                const auto cg = MDE_G(double, I.cp) + tc;
+                for (int idx = tid; idx < nm * WT; idx += nthr)
+                    tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
+                for (int idx = tid; idx < 4 * m * WT; idx += nthr)
+                    gs[(idx / WT) * WTP + idx % WT] = (TT)gg[idx];
+                for (int idx = tid; idx < n * WT; idx += nthr)
+                    cs[(idx / WT) * WTP + idx % WT] = (TT)cg[idx];
+            } else {
+                const auto Tg = MDE_G(float, I.Tp32) + tn;
+                const auto gg = MDE_G(float, I.g32) + tg;
+                const auto cg = MDE_G(float, I.cp32) + tc;
+                for (int idx = tid; idx < nm * WT; idx += nthr)
+                    tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
+                for (int idx = tid; idx < 4 * m * WT; idx += nthr)
+                    gs[(idx / WT) * WTP + idx % WT] = (TT)gg[idx];
+                for (int idx = tid; idx < n * WT; idx += nthr)
+                    cs[(idx / WT) * WTP + idx % WT] = (TT)cg[idx];
+            }
+        } else {
+            const double *tabd = it.spin == 0 ? tab0 : tab1;
+            if (tabd) {
+                // caller's tables, per-walker layout [W][n][m]
+                for (int idx = tid; idx < nm * WT; idx += nthr) {
+                    const int l = idx / nm, e = idx - l * nm, w = w0 + l;
+                    tabs[e * WTP + l] = (w < W) ? (TT)MDE_G(double, tabd)[(size_t)w * nm + e] : TT(0);
+                }
+            } else {
+                const size_t tn = (size_t)it.tile * nm * WT;
+                if (sizeof(TT) == 8) {
+                    const auto Tg = MDE_G(double, S.T) + tn;
+                    for (int idx = tid; idx < nm * WT; idx += nthr)
+                        tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
+                } else {
+                    const auto Tg = MDE_G(float, S.T32) + tn;
+                    for (int idx = tid; idx < nm * WT; idx += nthr)
+                        tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
+                }
+            }
+        }
+        __syncthreads();
+        double rhoA[4] = {0, 0, 0, 0};
+        double acc[NSUM] = {0, 0, 0, 0, 0};
+        if (MODE == DM_PROPOSE) {
+            const int w = w0 + wl;
+            if (w < W) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) rhoA[a] = MDE_G(double, I.rhoA)[(size_t)w * 4 + a];
+            }
+        }
+        switch (it.order) {
+            case 1: det_loop<1, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
+            case 2: det_loop<2, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
+            case 3: det_loop<3, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
+            case 4: det_loop<4, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
+            default: det_loop<0, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
+        }
+        __syncthreads();   // tables no longer needed: reuse LDS for the reduction
+        if (MODE == DM_PROPOSE) {
+            // lanes with the same wl hold sums over different excitation
+            // slots: fixed butterfly over the slot bits, then over waves
+#pragma unroll
+            for (int off = WT; off < 64; off <<= 1)
+#pragma unroll
+                for (int q = 0; q < NSUM; ++q) acc[q] += __shfl_xor(acc[q], off, 64);
+            double *red = reinterpret_cast<double *>(tab_raw);
+            const int wave = tid >> 6, lane = tid & 63;
+            const int nw = nthr >> 6;
+            if (lane < WT) {
+#pragma unroll
+                for (int q = 0; q < NSUM; ++q) red[(wave * WT + lane) * NSUM + q] = acc[q];
+            }
+            __syncthreads();
+            const auto part = MDE_GW(double, S.partial);
+            for (int idx = tid; idx < WT * NSUM; idx += nthr) {
+                const int l = idx / NSUM, q = idx - l * NSUM;
+                double s = 0.0;
+                for (int v = 0; v < nw; ++v) s += red[(v * WT + l) * NSUM + q];
+                part[((size_t)it.slot * WT + l) * NSUM + q] = s;
+            }
+            __syncthreads();
+        }
+    }
+    // the last block out resets the queue for the next launch
+    if (tid == 0) {
+        __threadfence();
+        const int done = atomicAdd(&counter[1], 1);
+        if (done == (int)gridDim.x - 1) {
+            atomicExch(&counter[0], 0);
+            atomicExch(&counter[1], 0);
+        }
+    }
+}
+
+template <typename TT, int MODE>
+static hipError_t launch_det_wt(int WT, hipStream_t st, const InstDev *d_insts,
+                                const WorkItem *items, int n_items, int ex_cap,
+                                const MoveArgs *d_moves, const MoveArgs &m1, size_t lds,
+                                int threads, int grid, int32_t *counter, const double *t0,
+                                const double *t1) {
+#define MDE_DET_CASE(X)                                                                     \
+    case X: {                                                                               \
+        auto fn = k_det<TT, MODE, X>;                                                       \
+        if (lds > 65536)                                                                    \
+            (void)hipFuncSetAttribute((const void *)fn,                                     \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds, st, d_insts, items, n_items,  \
+                           ex_cap, d_moves, m1, counter, t0, t1);                           \
+        return hipGetLastError();                                                           \
+    }
+    switch (WT) {
+        MDE_DET_CASE(1)
+        MDE_DET_CASE(2)
+        MDE_DET_CASE(4)
+        MDE_DET_CASE(8)
+        MDE_DET_CASE(16)
+        MDE_DET_CASE(32)
+        MDE_DET_CASE(64)
+        default: return hipErrorInvalidValue;
+    }
+#undef MDE_DET_CASE
+}
+
+hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst, const WorkItem *items,
+                      int n_items, int ex_cap, const MoveArgs *d_moves, const MoveArgs &m1, int mode,
+                      int prec, int WT, size_t lds, int threads, int grid, int32_t *counter,
+                      const double *tab0, const double *tab1) {
+    // every instance of one launch uses the same walker tile WT
+    (void)n_inst;
+    if (n_items <= 0) return hipSuccess;
+    if (prec == 0) {
+        if (mode == DM_PROPOSE)
+            return launch_det_wt<double, DM_PROPOSE>(WT, st, d_insts, items, n_items, ex_cap, d_moves,
+                                                     m1, lds, threads, grid, counter, tab0, tab1);
+        return launch_det_wt<double, DM_VALUES>(WT, st, d_insts, items, n_items, ex_cap, d_moves, m1,
+                                                lds, threads, grid, counter, tab0, tab1);
+    }
+    if (mode == DM_PROPOSE)
+        return launch_det_wt<float, DM_PROPOSE>(WT, st, d_insts, items, n_items, ex_cap, d_moves, m1,
+                                                lds, threads, grid, counter, tab0, tab1);
+    return launch_det_wt<float, DM_VALUES>(WT, st, d_insts, items, n_items, ex_cap, d_moves, m1,
+                                           lds, threads, grid, counter, tab0, tab1);
+}
+
+// ---------------------------------------------------------------------------
+// CI precontraction: C_sigma[u] = sum over CI terms with this spin's
+// excitation u of c_I R_other[d(I)] -- an exact regrouping of the CI sum of
+// Sec. III by the moving spin's excitation (R_other does not change while
+// electrons of spin sigma move).  Terms are visited in a fixed order, four
+// independent loads at a time.
+// ---------------------------------------------------------------------------
+
+__global__ void k_coef_gather(const InstDev *__restrict__ insts, const double *__restrict__ coef) {
+    const InstDev &I = insts[0];
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)I.n_det) return;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+        MDE_GW(double, I.s[s].coef_s)[k] = MDE_G(double, coef)[MDE_G(int32_t, I.s[s].ci_idx)[k]];
+}
+
+hipError_t launch_coef_gather(hipStream_t st, const InstDev *d_inst, const InstDev &h,
+                              const double *coef) {
+    const size_t n = (size_t)h.n_det;
+    hipLaunchKernelGGL(k_coef_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d_inst,
+                       coef);
+    return hipGetLastError();
+}
+
+// Work units: chunks of consecutive excitations whose CI segments are short
+// (chunk boundaries fall on excitation boundaries, about 64 terms each), and
+// pieces of at most 64 terms of the long segments (the reference excitation
+// is shared by every determinant that excites only the other spin).  A
+// thread streams the terms of its unit for one walker, eight independent
+// loads at a time; chunk units write C[u] directly, piece units write
+// partial sums that k_pc_fix adds in piece order.
+template <int WT>
+__global__ void __launch_bounds__(256)
+k_precontract(const InstDev *__restrict__ insts, int spin) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[spin];
+    const SpinDev &O = I.s[1 - spin];
+    constexpr int per_block = 256 / WT;
+    const int wl = threadIdx.x % WT;
+    int unit = blockIdx.y * per_block + threadIdx.x / WT;
+    if (WT == 64) unit = __builtin_amdgcn_readfirstlane(unit);
+    const int t = blockIdx.x;
+    if (unit >= S.n_chunks + S.n_pieces) return;
+    const auto seg = MDE_G(int32_t, S.ci_seg);
+    const auto oth = MDE_G(int32_t, S.ci_other);
+    const auto cf = MDE_G(double, S.coef_s);
+    const auto Ro = MDE_G(double, O.R) + (size_t)t * O.U * WT + wl;
+    int u, u1, k0, k1, kend;
+    double *out;
+    size_t ostride;
+    if (unit < S.n_chunks) {
+        u = S.chunks[2 * unit];
+        u1 = S.chunks[2 * unit + 1];
+        k0 = seg[u];
+        k1 = seg[u1];
+        kend = seg[u + 1];
+        out = S.C + (size_t)t * S.U * WT + wl;
+        ostride = WT;
+    } else {
+        const int4 pc = S.pieces[unit - S.n_chunks];
+        u = 0;
+        u1 = 1;
+        k0 = pc.y;
+        k1 = pc.z;
+        kend = pc.z;
+        out = S.pc_part + ((size_t)(unit - S.n_chunks) * S.n_tiles + t) * WT + wl;
+        ostride = 0;
+    }
+    const auto Cw = MDE_GW(double, out);
+    double s = 0.0;
+    for (int k = k0; k < k1; k += 8) {
+        int o[8];
+        double c[8], r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool ok = k + j < k1;
+            o[j] = ok ? oth[k + j] : 0;
+            c[j] = ok ? cf[k + j] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = (k + j < k1) ? Ro[(size_t)o[j] * WT] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (k + j < k1) {
+                while (k + j >= kend) {
+                    Cw[(size_t)u * ostride] = s;
+                    s = 0.0;
+                    ++u;
+                    kend = seg[u + 1];
+                }
+                s = fma(c[j], r[j], s);
+            }
+        }
+    }
+    for (; u < u1; ++u) {
+        Cw[(size_t)u * ostride] = s;
+        s = 0.0;
+    }
+}
+
+// C[u] of each long segment = sum of its pieces' partial sums, in order
+__global__ void __launch_bounds__(256) k_pc_fix(const InstDev *__restrict__ insts, int spin) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[spin];
+    const int WT = S.WT;
+    const int idx = blockIdx.y * 256 + threadIdx.x;
+    const int lg = idx / WT, wl = idx % WT, t = blockIdx.x;
+    if (lg >= S.n_longs) return;
+    const int4 L = S.longs[lg];
+    double s = 0.0;
+    for (int p = L.y; p < L.z; ++p)
+        s += MDE_G(double, S.pc_part)[((size_t)p * S.n_tiles + t) * WT + wl];
+    MDE_GW(double, S.C)[((size_t)t * S.U + L.x) * WT + wl] = s;
+}
+
+hipError_t launch_precontract(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
+                              const double *coef) {
+    (void)coef;
+    const SpinDev &S = h.s[spin];
+    const int per_block = 256 / S.WT;
+    const int units = S.n_chunks + S.n_pieces;
+    // tiles fastest: consecutive blocks work on different walker tiles
+    dim3 grid(S.n_tiles, (units + per_block - 1) / per_block);
+#define MDE_PC(X)                                                                       \
+    case X:                                                                             \
+        hipLaunchKernelGGL(k_precontract<X>, grid, dim3(256), 0, st, d_inst, spin);     \
+        break;
+    switch (S.WT) {
+        MDE_PC(1) MDE_PC(2) MDE_PC(4) MDE_PC(8) MDE_PC(16) MDE_PC(32) MDE_PC(64)
+        default: return hipErrorInvalidValue;
+    }
+#undef MDE_PC
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || S.n_longs == 0) return e;
+    dim3 g2(S.n_tiles, (S.n_longs * S.WT + 255) / 256);
+    hipLaunchKernelGGL(k_pc_fix, g2, dim3(256), 0, st, d_inst, spin);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// N = sum_u C_up[u] R_up[u] per walker (thread per walker, u ascending),
+// log|Psi| = log|D0up| + log|D0dn| + log|N|.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(1024)
+k_nsum(const InstDev *__restrict__ insts, double *log_abs_psi, double *sign_psi, int32_t *status,
+       int with_ref) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[0];
+    const int WT = S.WT, t = blockIdx.x;
+    const int wl = threadIdx.x % WT, slot = threadIdx.x / WT, nslot = blockDim.x / WT;
+    const size_t base = (size_t)t * S.U * WT + wl;
+    const auto Cb = MDE_G(double, S.C) + base;
+    const auto Rb = MDE_G(double, S.R) + base;
+    double s = 0.0;
+    for (int u = slot; u < S.U; u += nslot) s = fma(Cb[(size_t)u * WT], Rb[(size_t)u * WT], s);
+    __shared__ double red[1024];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (slot != 0) return;
+    for (int v = 1; v < nslot; ++v) s += red[v * WT + wl];
+    const int w = t * WT + wl;
+    if (w >= I.W) return;
+    I.Nold[w] = s;
+    int bits = I.st[w];
+    if (!(s != 0.0) || !isfinite(s)) bits |= 8;
+    I.st[w] = bits;
+    double la = log(fabs(s));
+    double sg = (s > 0.0) ? 1.0 : (s < 0.0 ? -1.0 : 0.0);
+    if (with_ref) {
+        la += I.s[0].logdet[w] + I.s[1].logdet[w];
+        sg *= I.s[0].sgn[w] * I.s[1].sgn[w];
+    }
+    if (log_abs_psi) log_abs_psi[w] = la;
+    if (sign_psi) sign_psi[w] = sg;
+    if (status) status[w] |= bits;
+}
+
+hipError_t launch_nsum(hipStream_t st, const InstDev *d_inst, const InstDev &h,
+                       double *log_abs_psi, double *sign_psi, int32_t *status, int with_ref) {
+    const SpinDev &S = h.s[0];
+    const int threads = S.WT >= 16 ? 1024 : 256;
+    hipLaunchKernelGGL(k_nsum, dim3(S.n_tiles), dim3(threads), 0, st, d_inst, log_abs_psi, sign_psi,
+                       status, with_ref);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// finish: per walker, sum the partials of its tile in slot order and form
+// ratio = rho N'/N, grad = G^{x,y,z}/N', lap = G^L/N' (Sec. III ratio eq.,
+// Sec. IV eq. gradMDS); the reference excitation contributes C_0 (1, rho^a).
+// ---------------------------------------------------------------------------
+
+__global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves,
+                         MoveArgs m1) {
+    const int inst = blockIdx.y;
+    const InstDev &I = insts[inst];
+    const MoveArgs mv = moves ? moves[inst] : m1;
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= I.W) return;
+    const SpinDev &S = I.s[mv.spin];
+    const int WT = S.WT, t = w / WT, wl = w - t * WT;
+    const double C0 = MDE_G(double, S.C)[(size_t)t * S.U * WT + wl];
+    double sum[NSUM];
+    sum[0] = C0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) sum[1 + a] = C0 * MDE_G(double, I.rhoA)[(size_t)w * 4 + a];
+    const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
+    const auto part = MDE_G(double, S.partial);
+    for (int s = s0; s < s1; ++s) {
+#pragma unroll
+        for (int q = 0; q < NSUM; ++q) sum[q] += part[((size_t)s * WT + wl) * NSUM + q];
+    }
+    const double Np = sum[0];
+    const double rho = I.rho[w];
+    const double ratio = rho * Np / I.Nold[w];
+    const double inv = 1.0 / Np;
+    I.Nnew[w] = Np;
+    int bits = I.st[w] & 2;
+    if (!(Np != 0.0) || !isfinite(Np)) bits |= 8;
+    const double g0 = sum[1] * inv, g1 = sum[2] * inv, g2 = sum[3] * inv, lp = sum[4] * inv;
+    if (!isfinite(ratio) || !isfinite(g0) || !isfinite(g1) || !isfinite(g2) || !isfinite(lp))
+        bits |= 4;
+    if (mv.ratio) mv.ratio[w] = ratio;
+    if (mv.grad) {
+        mv.grad[(size_t)w * 3 + 0] = g0;
+        mv.grad[(size_t)w * 3 + 1] = g1;
+        mv.grad[(size_t)w * 3 + 2] = g2;
+    }
+    if (mv.lap) mv.lap[w] = lp;
+    if (mv.status && bits) mv.status[w] |= bits;
+}
+
+hipError_t launch_finish(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
+                         const MoveArgs *d_moves, const MoveArgs &m1, int32_t *counter) {
+    (void)counter;
+    const int threads = 256;
+    hipLaunchKernelGGL(k_finish, dim3((maxW + threads - 1) / threads, n_inst), dim3(threads), 0, st,
+                       d_insts, d_moves, m1);
+    return hipGetLastError();
+}
+
+}  // namespace mde

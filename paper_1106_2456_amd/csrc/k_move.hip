@@ -1,0 +1,686 @@
+// Per-walker kernels: reference LU and inverse (Sec. III: computed from
+// scratch once), the table GEMM T_V = A^-1 Phi_V (Sec. III table; Algorithm 1
+// step 3; Sec. V: one matrix multiplication), the single-move proposal
+// (Algorithm 1 step 1 with the Sec. III Sherman-Morrison update written for a
+// row change, and the Sec. IV-A derivative factors), and the commit.
+#include "mde_internal.h"
+
+namespace mde {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// LU with partial pivoting and explicit inverse, one wave per matrix
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(64)
+k_lu_inverse(const InstDev *__restrict__ insts, int spin, const double *__restrict__ orb_in,
+             int32_t *status) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[spin];
+    const int w = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int n = S.n, no = S.no, ld = n + 1;
+    extern __shared__ double sh[];
+    double *A = sh;
+    double *X = sh + n * ld;
+    __shared__ int pv[MAXN];
+    if (orb_in) {
+        for (int idx = lane; idx < n * no; idx += 64) {
+            const int i = idx / no, p = idx - i * no;
+            const double v = orb_in[((size_t)(w * n + i) * 5) * no + p];
+            S.Phi[(size_t)w * n * no + idx] = v;
+            if (I.prec == 1 && p >= n)
+                S.PhiV32[((size_t)w * n + i) * S.m + (p - n)] = (float)v;
+        }
+    } else if (I.prec == 1) {
+        for (int idx = lane; idx < n * S.m; idx += 64) {
+            const int i = idx / S.m, p = idx - i * S.m;
+            S.PhiV32[(size_t)w * n * S.m + idx] = (float)S.Phi[((size_t)w * n + i) * no + n + p];
+        }
+    }
+    for (int idx = lane; idx < n * n; idx += 64) {
+        const int i = idx / n, j = idx - i * n;
+        A[i * ld + j] = orb_in ? orb_in[((size_t)(w * n + i) * 5) * no + j]
+                               : S.Phi[((size_t)w * n + i) * no + j];
+    }
+    __syncthreads();
+    double sg = 1.0, la = 0.0;
+    int sing = 0;
+    for (int k = 0; k < n; ++k) {
+        double v = (lane >= k && lane < n) ? fabs(A[lane * ld + k]) : -1.0;
+        int idx = lane;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ov = __shfl_xor(v, off, 64);
+            const int oi = __shfl_xor(idx, off, 64);
+            if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+        }
+        const int p = __builtin_amdgcn_readfirstlane(idx);
+        if (!(v > 0.0)) { sing = 1; break; }
+        if (p != k) {
+            if (lane < n) {
+                const double t = A[k * ld + lane];
+                A[k * ld + lane] = A[p * ld + lane];
+                A[p * ld + lane] = t;
+            }
+            sg = -sg;
+        }
+        if (lane == 0) pv[k] = p;
+        __syncthreads();
+        const double piv = A[k * ld + k];
+        if (piv < 0.0) sg = -sg;
+        la += log(fabs(piv));
+        if (lane > k && lane < n) {
+            const double f = A[lane * ld + k] / piv;
+            A[lane * ld + k] = f;
+            for (int j = k + 1; j < n; ++j) A[lane * ld + j] = fma(-f, A[k * ld + j], A[lane * ld + j]);
+        }
+        __syncthreads();
+    }
+    double *Bw = S.B + (size_t)w * n * n;
+    if (sing) {
+        for (int idx = lane; idx < n * n; idx += 64) Bw[idx] = 0.0;
+        if (lane == 0) {
+            S.logdet[w] = -INFINITY;
+            S.sgn[w] = 0.0;
+            I.st[w] |= 1;
+            if (status) status[w] |= 1;
+        }
+        return;
+    }
+    if (lane < n) {
+        const int c = lane;
+        for (int i = 0; i < n; ++i) X[i * ld + c] = (i == c) ? 1.0 : 0.0;
+        for (int k = 0; k < n; ++k) {
+            const int p = pv[k];
+            if (p != k) {
+                const double t = X[k * ld + c];
+                X[k * ld + c] = X[p * ld + c];
+                X[p * ld + c] = t;
+            }
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = X[i * ld + c];
+            for (int kk = 0; kk < i; ++kk) s = fma(-A[i * ld + kk], X[kk * ld + c], s);
+            X[i * ld + c] = s;
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = X[i * ld + c];
+            for (int kk = i + 1; kk < n; ++kk) s = fma(-A[i * ld + kk], X[kk * ld + c], s);
+            X[i * ld + c] = s / A[i * ld + i];
+        }
+    }
+    __syncthreads();
+    for (int idx = lane; idx < n * n; idx += 64) {
+        const int i = idx / n, j = idx - i * n;
+        Bw[idx] = X[i * ld + j];
+    }
+    if (lane == 0) {
+        S.logdet[w] = la;
+        S.sgn[w] = sg;
+    }
+}
+
+hipError_t launch_lu_inverse(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
+                             const double *orb_in, int32_t *status) {
+    const int n = h.s[spin].n;
+    const size_t lds = sizeof(double) * 2 * n * (n + 1);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_lu_inverse,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_lu_inverse, dim3(h.W), dim3(64), lds, st, d_inst, spin, orb_in, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// table GEMM in FP64: T_V[w] = A^-1[w] Phi_V[w], one block per walker,
+// 64-column chunks of Phi_V staged in LDS.  In MIXED mode the FP32 table is
+// the rounded FP64 product at a refresh.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_table_gemm(const InstDev *__restrict__ insts, int spin) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[spin];
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int n = S.n, m = S.m, no = S.no;
+    extern __shared__ double sh[];
+    double *Bs = sh;              // n*n
+    double *Pv = sh + n * n;      // n*64
+    for (int idx = tid; idx < n * n; idx += 256) Bs[idx] = S.B[(size_t)w * n * n + idx];
+    for (int c0 = 0; c0 < m; c0 += 64) {
+        __syncthreads();
+        for (int idx = tid; idx < n * 64; idx += 256) {
+            const int k = idx >> 6, pp = idx & 63;
+            Pv[idx] = (c0 + pp < m) ? S.Phi[((size_t)w * n + k) * no + n + c0 + pp] : 0.0;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < n * 64; idx += 256) {
+            const int r = idx >> 6, pp = idx & 63;
+            if (c0 + pp >= m) continue;
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s = fma(Bs[r * n + k], Pv[k * 64 + pp], s);
+            const int WT = S.WT;
+            const size_t o = (((size_t)(w / WT) * n + r) * m + c0 + pp) * WT + (w % WT);
+            if (I.prec == 0) S.T[o] = s;
+            else S.T32[o] = (float)s;
+        }
+    }
+}
+
+hipError_t launch_table_gemm(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin) {
+    const int n = h.s[spin].n;
+    const size_t lds = sizeof(double) * (n * n + n * 64);
+    hipLaunchKernelGGL(k_table_gemm, dim3(h.W), dim3(256), lds, st, d_inst, spin);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// proposal, FP64: one block per walker tile, walker index fastest.
+//   c = A^-1 e_i, rho = a'.c (= det A'/det A), c' = c/rho,
+//   q = a'^T T_V - phi'_V,   T'_V = T_V - c' q^T   (Sec. III SM eqs., row form),
+//   rho^a = d^a_O . c',  g^a = d^a_V - d^a_O^T T'_V = d^a_V - d^a_O^T T_V + rho^a q
+// T'_V, g^a and c' are written walker-tiled, the layout the determinant
+// kernel stages into LDS.
+// ---------------------------------------------------------------------------
+
+template <int WT>
+__global__ void __launch_bounds__(1024)
+k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1) {
+    const int inst = blockIdx.y;
+    const InstDev &I = insts[inst];
+    const MoveArgs mv = moves ? moves[inst] : m1;
+    const SpinDev &S = I.s[mv.spin];
+    const int t = blockIdx.x;
+    if (t >= S.n_tiles) return;
+    const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nm = n * m;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    extern __shared__ double shp[];
+    double *c_s = shp;                 // [n][WT]
+    double *a_s = c_s + n * WT;        // [n][WT]
+    double *d_s = a_s + n * WT;        // [4][n][WT]
+    double *ir_s = d_s + 4 * n * WT;   // [WT] 1/rho
+    double *rA_s = ir_s + WT;          // [4][WT]
+    const auto B = MDE_G(double, S.B);
+    const auto orb = MDE_G(double, mv.new_orb);
+    for (int idx = tid; idx < n * WT; idx += nthr) {
+        const int r = idx / WT, l = idx % WT, w = t * WT + l;
+        double c = 0.0, a = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        if (w < W) {
+            const auto nr = orb + (size_t)w * 5 * no;
+            c = B[((size_t)w * n + r) * n + row];
+            a = nr[r];
+            d0 = nr[no + r];
+            d1 = nr[2 * no + r];
+            d2 = nr[3 * no + r];
+            d3 = nr[4 * no + r];
+        }
+        c_s[idx] = c;
+        a_s[idx] = a;
+        d_s[idx] = d0;
+        d_s[n * WT + idx] = d1;
+        d_s[2 * n * WT + idx] = d2;
+        d_s[3 * n * WT + idx] = d3;
+    }
+    __syncthreads();
+    if (tid < WT) {
+        const int l = tid, w = t * WT + l;
+        double rho = 0.0, dc[4] = {0, 0, 0, 0};
+        for (int r = 0; r < n; ++r) {
+            const double c = c_s[r * WT + l];
+            rho = fma(a_s[r * WT + l], c, rho);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) dc[a] = fma(d_s[(a * n + r) * WT + l], c, dc[a]);
+        }
+        const double irho = (w < W) ? 1.0 / rho : 0.0;
+        ir_s[l] = irho;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) rA_s[a * WT + l] = dc[a] * irho;
+        if (w < W) {
+            I.rho[w] = rho;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) I.rhoA[(size_t)w * 4 + a] = dc[a] * irho;
+            const int bits = (!isfinite(rho) || fabs(rho) < 1e-300) ? 2 : 0;
+            I.st[w] = (I.st[w] & ~2) | bits;
+        }
+    }
+    __syncthreads();
+    const auto Tt = MDE_G(double, S.T) + (size_t)t * nm * WT;
+    const auto Tpt = MDE_GW(double, I.Tp) + (size_t)t * nm * WT;
+    const auto gt = MDE_GW(double, I.g) + (size_t)t * 4 * m * WT;
+    const auto cpt = MDE_GW(double, I.cp) + (size_t)t * n * WT;
+    for (int idx = tid; idx < n * WT; idx += nthr) cpt[idx] = c_s[idx] * ir_s[idx % WT];
+    for (int idx = tid; idx < m * WT; idx += nthr) {
+        const int p = idx / WT, l = idx % WT, w = t * WT + l;
+        double v = 0.0, wa[4] = {0, 0, 0, 0};
+        for (int r = 0; r < n; ++r) {
+            const double tv = Tt[(size_t)(r * m + p) * WT + l];
+            v = fma(a_s[r * WT + l], tv, v);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) wa[a] = fma(d_s[(a * n + r) * WT + l], tv, wa[a]);
+        }
+        double q = 0.0;
+        double dv[4] = {0, 0, 0, 0};
+        if (w < W) {
+            const auto nr = orb + (size_t)w * 5 * no + n + p;
+            q = v - nr[0];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) dv[a] = nr[(1 + a) * no];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            gt[(size_t)(a * m + p) * WT + l] = (w < W) ? dv[a] - wa[a] + rA_s[a * WT + l] * q : 0.0;
+        const double qi = q * ir_s[l];
+        for (int r = 0; r < n; ++r) {
+            const size_t o = (size_t)(r * m + p) * WT + l;
+            Tpt[o] = fma(-c_s[r * WT + l], qi, Tt[o]);
+        }
+    }
+    for (int idx = tid; idx < no * WT; idx += nthr) {
+        const int p = idx / WT, l = idx % WT, w = t * WT + l;
+        if (w < W) I.newrow[(size_t)w * I.nomax + p] = orb[(size_t)w * 5 * no + p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// proposal, MIXED (Algorithm 1 as written: update the inverse, then rebuild
+// the table with one GEMM).  FP64 part, one wave per walker:
+//   c = A^-1 e_i, rho = a'.c, c' = c/rho, r = a'^T A^-1,
+//   A'^-1 = A^-1 - c' (r - e_i^T)                  -> FP32 operand rows 0..n-1
+//   e^a = d^a_O^T A'^-1 = d^a_O^T A^-1 - rho^a (r - e_i^T)  -> rows n..n+3
+// The GEMM kernel below then forms T'_V = A'^-1 Phi'_V and g^a = d^a_V - e^a Phi'_V.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_propose_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1) {
+    const int inst = blockIdx.y;
+    const InstDev &I = insts[inst];
+    const MoveArgs mv = moves ? moves[inst] : m1;
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= I.W) return;
+    const SpinDev &S = I.s[mv.spin];
+    const int n = S.n, no = S.no, row = mv.row, nmax = I.nmax;
+    const double *__restrict__ nr = mv.new_orb + (size_t)w * 5 * no;
+    const double *__restrict__ Bw = S.B + (size_t)w * n * n;
+    double c = 0.0, ap = 0.0, d[4] = {0, 0, 0, 0};
+    if (lane < n) {
+        c = Bw[(size_t)lane * n + row];
+        ap = nr[lane];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) d[a] = nr[(1 + a) * no + lane];
+    }
+    const double rho = wave_sum(ap * c);
+    double dc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) dc[a] = wave_sum(d[a] * c);
+    const double irho = 1.0 / rho;
+    double rhoA[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) rhoA[a] = dc[a] * irho;
+    if (lane < n) {
+        const int WT = S.WT;
+        const size_t o = ((size_t)(w / WT) * n + lane) * WT + (w % WT);
+        I.cp[o] = c * irho;
+        I.cp32[o] = (float)(c * irho);
+    }
+    if (lane == 0) {
+        I.rho[w] = rho;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) I.rhoA[(size_t)w * 4 + a] = rhoA[a];
+        int bits = 0;
+        if (!isfinite(rho) || fabs(rho) < 1e-300) bits |= 2;
+        I.st[w] = (I.st[w] & ~2) | bits;
+    }
+    float *__restrict__ Ap = I.Ap32 + (size_t)w * (nmax + 4) * nmax;
+    if (lane < n) {
+        const int j = lane;
+        double r = 0.0, f[4] = {0, 0, 0, 0};
+        for (int k = 0; k < n; ++k) {
+            const double b = Bw[(size_t)k * n + j];
+            r = fma(nr[k], b, r);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) f[a] = fma(nr[(1 + a) * no + k], b, f[a]);
+        }
+        const double rd = r - (j == row ? 1.0 : 0.0);
+        for (int rr = 0; rr < n; ++rr) {
+            const double cpr = Bw[(size_t)rr * n + row] * irho;
+            Ap[(size_t)rr * nmax + j] = (float)fma(-cpr, rd, Bw[(size_t)rr * n + j]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) Ap[(size_t)(n + a) * nmax + j] = (float)fma(-rhoA[a], rd, f[a]);
+    }
+    for (int p = lane; p < no; p += 64) I.newrow[(size_t)w * I.nomax + p] = nr[p];
+}
+
+// FP32 MFMA GEMM of the mixed proposal: one block (4 waves) per walker.
+// Operand rows (n + 4) x K=n from Ap32, Phi'_V = Phi_V with row i replaced by
+// the new values, both staged in LDS; v_mfma_f32_16x16x4f32 tiles (A: lane l
+// holds A[l%16][l/16]; B: B[l/16][l%16]; D: lane l, element i holds
+// D[4(l/16)+i][l%16]).
+__global__ void __launch_bounds__(256)
+k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1) {
+    const int inst = blockIdx.y;
+    const InstDev &I = insts[inst];
+    const MoveArgs mv = moves ? moves[inst] : m1;
+    const int w = blockIdx.x;
+    if (w >= I.W) return;
+    const SpinDev &S = I.s[mv.spin];
+    const int n = S.n, m = S.m, no = S.no, row = mv.row, nmax = I.nmax, mmax = I.mmax;
+    const int rows = n + 4;
+    const int rp = (rows + 15) & ~15, kp = (n + 3) & ~3, mp = (m + 15) & ~15;
+    const int lda = kp + 1;
+    extern __shared__ float shf[];
+    float *As = shf;                 // rp x lda
+    float *Bs = shf + rp * lda;      // kp x mp
+    const int tid = threadIdx.x;
+    const float *__restrict__ Ap = I.Ap32 + (size_t)w * (nmax + 4) * nmax;
+    for (int idx = tid; idx < rp * kp; idx += 256) {
+        const int r = idx / kp, k = idx - r * kp;
+        As[r * lda + k] = (r < rows && k < n) ? Ap[(size_t)r * nmax + k] : 0.0f;
+    }
+    const double *__restrict__ nr = mv.new_orb + (size_t)w * 5 * no;
+    const float *__restrict__ Pv = S.PhiV32 + (size_t)w * n * m;
+    for (int idx = tid; idx < kp * mp; idx += 256) {
+        const int k = idx / mp, p = idx - k * mp;
+        float v = 0.0f;
+        if (k < n && p < m) v = (k == row) ? (float)nr[n + p] : Pv[(size_t)k * m + p];
+        Bs[idx] = v;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int RT = rp >> 4, CT = mp >> 4;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int WT = S.WT, tw = w / WT, lw = w % WT;
+    float *__restrict__ Tp = I.Tp32 + (size_t)tw * n * m * WT + lw;
+    float *__restrict__ g32 = I.g32 + (size_t)tw * 4 * m * WT + lw;
+    for (int t = wave; t < RT * CT; t += 4) {
+        const int rt = t / CT, ct = t - rt * CT;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kk = 0; kk < kp; kk += 4) {
+            const float a = As[(rt * 16 + lr) * lda + kk + lk];
+            const float b = Bs[(kk + lk) * mp + ct * 16 + lr];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = rt * 16 + 4 * lk + i, p = ct * 16 + lr;
+            if (p >= m) continue;
+            if (r < n) Tp[(size_t)(r * m + p) * WT] = acc[i];
+            else if (r < rows) {
+                const int a = r - n;
+                g32[(size_t)(a * m + p) * WT] = (float)nr[(1 + a) * no + n + p] - acc[i];
+            }
+        }
+    }
+}
+
+hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
+                          const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
+                          int mmax, int WT, int max_tiles) {
+    if (prec == 0) {
+        const int threads = WT >= 16 ? 1024 : 256;
+        const size_t lds = sizeof(double) * ((size_t)6 * nmax * WT + 5 * WT);
+        dim3 g(max_tiles, n_inst);
+#define MDE_PP(X)                                                                             \
+    case X:                                                                                   \
+        if (lds > 65536)                                                                      \
+            (void)hipFuncSetAttribute((const void *)k_propose64<X>,                           \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
+        hipLaunchKernelGGL(k_propose64<X>, g, dim3(threads), lds, st, d_insts, d_moves, m1); \
+        break;
+        switch (WT) {
+            MDE_PP(1) MDE_PP(2) MDE_PP(4) MDE_PP(8) MDE_PP(16) MDE_PP(32) MDE_PP(64)
+            default: return hipErrorInvalidValue;
+        }
+#undef MDE_PP
+        return hipGetLastError();
+    }
+    dim3 grid((maxW + 3) / 4, n_inst);
+    hipLaunchKernelGGL(k_propose_mixed, grid, dim3(256), 0, st, d_insts, d_moves, m1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int rp = (nmax + 4 + 15) & ~15, kp = (nmax + 3) & ~3, mp = (mmax + 15) & ~15;
+    const size_t lds = sizeof(float) * ((size_t)rp * (kp + 1) + (size_t)kp * mp);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_gemm_mixed,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_gemm_mixed, dim3(maxW, n_inst), dim3(256), lds, st, d_insts, d_moves, m1);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// commit (Sec. III SM eq., row form): for accepted walkers
+//   A^-1 <- A^-1 - c' (a'^T A^-1 - e_i^T),  T_V <- T'_V,  Phi row i <- new,
+//   log|det A| += log|rho|, N <- N'.  One block per walker tile.
+// ---------------------------------------------------------------------------
+
+template <int WT>
+__global__ void __launch_bounds__(1024)
+k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1) {
+    const int inst = blockIdx.y;
+    const InstDev &I = insts[inst];
+    const MoveArgs mv = moves ? moves[inst] : m1;
+    const SpinDev &S = I.s[mv.spin];
+    const int t = blockIdx.x;
+    if (t >= S.n_tiles) return;
+    const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nm = n * m;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    extern __shared__ double sha[];
+    double *rs = sha;              // [n][WT]  a'^T A^-1 - e_i^T
+    double *cps = rs + n * WT;     // [n][WT]  c'
+    __shared__ int acc_s[64];
+    if (tid < WT) {
+        const int w = t * WT + tid;
+        acc_s[tid] = (w < W) ? (int)mv.accept[w] : 0;
+    }
+    __syncthreads();
+    const auto nrow = MDE_G(double, I.newrow);
+    for (int idx = tid; idx < n * WT; idx += nthr) {
+        const int j = idx / WT, l = idx % WT, w = t * WT + l;
+        double r = 0.0, c = 0.0;
+        if (acc_s[l]) {
+            const auto Bw = MDE_G(double, S.B) + (size_t)w * n * n;
+            const auto nr = nrow + (size_t)w * I.nomax;
+            for (int k = 0; k < n; ++k) r = fma(nr[k], Bw[(size_t)k * n + j], r);
+            r -= (j == row) ? 1.0 : 0.0;
+            c = MDE_G(double, I.cp)[((size_t)t * n + j) * WT + l];
+        }
+        rs[idx] = r;
+        cps[idx] = c;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * n * WT; idx += nthr) {
+        const int l = idx % WT, rj = idx / WT, r = rj / n, j = rj - r * n;
+        if (!acc_s[l]) continue;
+        const size_t o = ((size_t)(t * WT + l) * n + r) * n + j;
+        S.B[o] = fma(-cps[r * WT + l], rs[j * WT + l], S.B[o]);
+    }
+    const size_t tb = (size_t)t * nm * WT;
+    if (I.prec == 0) {
+        for (int idx = tid; idx < nm * WT; idx += nthr)
+            if (acc_s[idx % WT]) S.T[tb + idx] = I.Tp[tb + idx];
+    } else {
+        for (int idx = tid; idx < nm * WT; idx += nthr)
+            if (acc_s[idx % WT]) S.T32[tb + idx] = I.Tp32[tb + idx];
+        for (int idx = tid; idx < m * WT; idx += nthr) {
+            const int p = idx / WT, l = idx % WT, w = t * WT + l;
+            if (acc_s[l]) S.PhiV32[((size_t)w * n + row) * m + p] = (float)nrow[(size_t)w * I.nomax + n + p];
+        }
+    }
+    for (int idx = tid; idx < no * WT; idx += nthr) {
+        const int p = idx / WT, l = idx % WT, w = t * WT + l;
+        if (acc_s[l]) S.Phi[((size_t)w * n + row) * no + p] = nrow[(size_t)w * I.nomax + p];
+    }
+    if (tid < WT && acc_s[tid]) {
+        const int w = t * WT + tid;
+        const double rho = I.rho[w];
+        S.logdet[w] += log(fabs(rho));
+        if (rho < 0.0) S.sgn[w] = -S.sgn[w];
+        I.Nold[w] = I.Nnew[w];
+    }
+}
+
+hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
+                         const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
+                         int mmax, int WT, int max_tiles) {
+    (void)prec; (void)mmax; (void)maxW;
+    const int threads = WT >= 16 ? 1024 : 256;
+    const size_t lds = sizeof(double) * 2 * (size_t)nmax * WT;
+    dim3 g(max_tiles, n_inst);
+#define MDE_AC(X)                                                                           \
+    case X:                                                                                 \
+        hipLaunchKernelGGL(k_accept<X>, g, dim3(threads), lds, st, d_insts, d_moves, m1);  \
+        break;
+    switch (WT) {
+        MDE_AC(1) MDE_AC(2) MDE_AC(4) MDE_AC(8) MDE_AC(16) MDE_AC(32) MDE_AC(64)
+        default: return hipErrorInvalidValue;
+    }
+#undef MDE_AC
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+
+__global__ void k_init_misc(const InstDev *__restrict__ insts) {
+    const InstDev &I = insts[0];
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int s = 0; s < 2; ++s) {
+        const SpinDev &S = I.s[s];
+        const size_t nt = (size_t)S.n_tiles * S.WT;
+        if (tid < nt) {
+            const size_t t = tid / S.WT, wl = tid % S.WT;
+            S.R[t * S.U * S.WT + wl] = 1.0;   // the reference: D_0 / D_0
+        }
+    }
+    if (tid < (size_t)I.W) I.st[tid] = 0;
+    if (tid < 2) I.counter[tid] = 0;
+}
+
+hipError_t launch_init_misc(hipStream_t st, const InstDev *d_inst, const InstDev &h) {
+    size_t nmax = (size_t)h.W + 64;
+    for (int s = 0; s < 2; ++s) {
+        const size_t nt = (size_t)h.s[s].n_tiles * h.s[s].WT;
+        if (nt > nmax) nmax = nt;
+    }
+    hipLaunchKernelGGL(k_init_misc, dim3((unsigned)((nmax + 255) / 256)), dim3(256), 0, st, d_inst);
+    return hipGetLastError();
+}
+
+__global__ void k_export(const InstDev *__restrict__ insts, int what, int spin, double *dst,
+                         const int32_t *__restrict__ perm_user, int n_user) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[spin];
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t W = I.W;
+    if (what == 0) {
+        if (tid < W * S.n * S.n) dst[tid] = S.B[tid];
+    } else if (what == 1) {
+        const size_t nm = (size_t)S.n * S.m;
+        if (tid < W * nm) {
+            const size_t w = tid / nm, e = tid % nm;
+            const size_t o = ((w / S.WT) * nm + e) * S.WT + w % S.WT;
+            dst[tid] = I.prec == 0 ? S.T[o] : (double)S.T32[o];
+        }
+    } else if (what == 2) {
+        if (tid < W * (size_t)n_user) {
+            const size_t w = tid / n_user, uu = tid % n_user;
+            const int u = perm_user[uu];
+            const size_t t = w / S.WT, wl = w % S.WT;
+            dst[tid] = S.R[(t * S.U + u) * S.WT + wl];
+        }
+    } else if (what == 3) {
+        if (tid < W) dst[tid] = S.logdet[tid];
+    } else if (what == 4) {
+        if (tid < W) dst[tid] = I.Nold[tid];
+    }
+}
+
+hipError_t launch_export(hipStream_t st, const InstDev *d_inst, const InstDev &h, int what,
+                         int spin, double *dst, const int32_t *perm_user) {
+    const SpinDev &S = h.s[spin];
+    size_t count = h.W;
+    if (what == 0) count = (size_t)h.W * S.n * S.n;
+    else if (what == 1) count = (size_t)h.W * S.n * S.m;
+    else if (what == 2) count = (size_t)h.W * S.U;
+    hipLaunchKernelGGL(k_export, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, d_inst,
+                       what, spin, dst, perm_user, S.U);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int32_t v, size_t n) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(hipStream_t st, int32_t *counter) {
+    return launch_fill_i32(st, counter, 0, 2);
+}
+
+// ---------------------------------------------------------------------------
+// synthetic orbitals: s-Gaussians chi_b = exp(-a |r - c_b|^2) with
+// grad chi = -2a (r - c) chi and lap chi = (4a^2 |r - c|^2 - 6a) chi, then
+// phi_p = sum_b mo[p][b] chi_b.  One block per position.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_sgauss(int nb, const double *__restrict__ centres, const double *__restrict__ expo, int n_orb,
+         const double *__restrict__ mo, const double *__restrict__ pos, double *__restrict__ out) {
+    extern __shared__ double chi[];   // [nb][5]
+    const int q = blockIdx.x;
+    const double x = pos[3 * (size_t)q], y = pos[3 * (size_t)q + 1], z = pos[3 * (size_t)q + 2];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double dx = x - centres[3 * b], dy = y - centres[3 * b + 1], dz = z - centres[3 * b + 2];
+        const double a = expo[b];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double v = exp(-a * r2);
+        chi[5 * b + 0] = v;
+        chi[5 * b + 1] = -2.0 * a * dx * v;
+        chi[5 * b + 2] = -2.0 * a * dy * v;
+        chi[5 * b + 3] = -2.0 * a * dz * v;
+        chi[5 * b + 4] = (4.0 * a * a * r2 - 6.0 * a) * v;
+    }
+    __syncthreads();
+    double *o = out + (size_t)q * 5 * n_orb;
+    for (int p = threadIdx.x; p < n_orb; p += blockDim.x) {
+        double acc[5] = {0, 0, 0, 0, 0};
+        const double *mp = mo + (size_t)p * nb;
+        for (int b = 0; b < nb; ++b) {
+            const double wgt = mp[b];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) acc[c] = fma(wgt, chi[5 * b + c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) o[(size_t)c * n_orb + p] = acc[c];
+    }
+}
+
+hipError_t launch_sgauss(hipStream_t st, int nb, const double *centres, const double *expo,
+                         int n_orb, const double *mo, int npos, const double *pos, double *out) {
+    if (npos <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) * 5 * nb;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_sgauss,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_sgauss, dim3(npos), dim3(256), lds, st, nb, centres, expo, n_orb, mo, pos,
+                       out);
+    return hipGetLastError();
+}
+
+}  // namespace mde

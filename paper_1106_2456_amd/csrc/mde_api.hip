@@ -1,0 +1,1460 @@
+// Host runtime and C ABI of libmde (see include/mde.h).
+//
+// A context owns host metadata only: the expansion in its internal order,
+// work-item plans and state flags.  All device memory is the caller's
+// workspace, carved here.  The evaluation calls only enqueue kernels (and,
+// for groups, one small host-to-device copy of per-instance arguments), so
+// they can be captured into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/mde.h"
+#include "mde_internal.h"
+
+using namespace mde;
+
+namespace {
+
+const char *kVersion = "mde 0.1 (gfx950)";
+
+struct SpinHost {
+    int n = 0, m = 0, no = 0, U = 0, max_order = 0;
+    bool have = false;
+    std::vector<int> perm;       // internal -> user excitation index
+    std::vector<int> iperm;      // user -> internal
+    std::vector<uint4> ex;       // packed records, internal order
+    std::vector<int> orders;     // order of each internal excitation
+    int order_start[MAXK + 2] = {0};
+    std::vector<int> ci_seg, ci_other, ci_idx;
+    std::vector<int> chunks;     // precontraction chunks (excitation boundaries)
+    std::vector<int4> pieces;    // pieces of long CI segments (u, k0, k1, 0)
+    std::vector<int4> longs;     // (u, first piece, end piece, 0)
+    std::vector<int> inv_off, inv_ent;
+    // plan
+    int item_exc = 0, threads = 0;
+    std::vector<WorkItem> items;     // scheduling order
+    std::vector<int> tile_slot;
+    size_t lds_prop = 0, lds_val = 0;
+    int grid = 0;
+    int ex_cap = 0;      // longest item (records staged in LDS)
+};
+
+struct Plan {
+    int WT, item_exc[2], threads[2];
+};
+
+}  // namespace
+
+struct mde_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void *> host_bufs;
+};
+
+struct mde_ctx {
+    mde_desc d{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    SpinHost sp[2];
+    int WT = 64;
+    std::vector<double> coef;
+    std::vector<int> up_idx, dn_idx;
+    int64_t n_det = 0;
+    bool have_ci = false;
+    int n_cu = 256;
+    // s-Gaussian basis per spin (optional)
+    int nb[2] = {0, 0};
+    std::vector<double> centres[2], expo[2], mo[2];
+    double *d_centres[2] = {nullptr, nullptr}, *d_expo[2] = {nullptr, nullptr},
+           *d_mo[2] = {nullptr, nullptr};
+    // device
+    int W = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    InstDev h{};
+    InstDev *d_inst = nullptr;
+    int32_t *d_perm_user[2] = {nullptr, nullptr};
+    WorkItem *d_items[2] = {nullptr, nullptr};
+    int32_t *d_tile_slot[2] = {nullptr, nullptr};
+    size_t items_cap[2] = {0, 0};
+    size_t partial_cap[2] = {0, 0};
+    size_t tileslot_cap[2] = {0, 0};
+    // state
+    bool initialized = false;
+    bool adjoint_state = false;
+    bool R_valid[2] = {false, false};
+    bool C_valid[2] = {false, false};
+    int pending_e = -1;
+    long accept_count = 0;
+    bool capturing = false;
+    const double *last_T[2] = {nullptr, nullptr};   // tables of the last mde_eval_tables
+};
+
+struct mde_group {
+    std::vector<mde_ctx *> ctx;
+    hipStream_t stream = nullptr;
+    int prec = 0, WT = 1, threads = 256, maxW = 0, nmax = 0, mmax = 0;
+    size_t lds = 0;
+    int grid = 0;
+    int ex_cap = 16;
+    InstDev *d_insts = nullptr;
+    MoveArgs *d_moves = nullptr;
+    WorkItem *d_items = nullptr;
+    int n_items = 0;
+    std::vector<MoveArgs> hmoves;
+    // pinned upload ring
+    static constexpr int RING = 64;
+    MoveArgs *pinned = nullptr;
+    hipEvent_t ev[RING] = {};
+    bool ev_used[RING] = {};
+    int ring_pos = 0;
+    bool capturing = false;
+    std::vector<void *> capture_bufs;
+    std::string err;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+#define MDE_FAIL(ctx, code, ...)                                    \
+    do {                                                           \
+        char _b[512];                                              \
+        snprintf(_b, sizeof(_b), __VA_ARGS__);                     \
+        if (ctx) (ctx)->err = _b;                                  \
+        return code;                                               \
+    } while (0)
+
+#define MDE_HIP(ctx, call)                                                          \
+    do {                                                                            \
+        hipError_t _e = (call);                                                     \
+        if (_e != hipSuccess)                                                       \
+            MDE_FAIL(ctx, MDE_DEVICE, "%s failed: %s", #call, hipGetErrorString(_e)); \
+    } while (0)
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = align_up(off, 256);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += sizeof(T) * std::max<size_t>(count, 1);
+        return p;
+    }
+};
+
+static int pow2_floor(int x) {
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+
+// relative cost of one excitation of order k in the determinant kernel
+static double order_cost(int k) {
+    static const double c[9] = {0, 13, 23, 45, 95, 300, 500, 800, 1200};
+    return c[std::min(std::max(k, 0), 8)];
+}
+
+static int spin_of(const mde_ctx *c, int e, int *row) {
+    if (e < c->d.n_elec[0]) {
+        *row = e;
+        return 0;
+    }
+    *row = e - c->d.n_elec[0];
+    return 1;
+}
+
+// bytes of LDS the determinant kernel needs: staged excitation records,
+// then the walker tile's tables (or the reduction scratch, whichever is larger)
+static size_t det_lds(const SpinHost &s, int WT, int threads, int prec, bool propose,
+                      int ex_cap = ITEM_MAX) {
+    const int WTP = (WT >= 8) ? WT + 1 : WT;
+    const size_t esz = prec == 0 ? 8 : 4;
+    size_t tab = (size_t)s.n * s.m * WTP * esz;
+    if (propose) tab += (size_t)(4 * s.m + s.n) * WTP * esz;
+    const size_t red = propose ? (size_t)(threads / 64) * WT * NSUM * 8 : 0;
+    return (size_t)ex_cap * 16 + std::max(tab, red);
+}
+
+// work items of one spin for a plan: per tile, per order, chunks of about
+// item_exc order-2-equivalent excitations (at least one per slot)
+static void build_items(const SpinHost &s, int W, int WT, int item_exc, int threads,
+                        std::vector<WorkItem> &items, std::vector<int> &tile_slot, int spin) {
+    items.clear();
+    const int n_tiles = (W + WT - 1) / WT;
+    tile_slot.assign(n_tiles + 1, 0);
+    const int nslot = threads / WT;
+    std::vector<WorkItem> per;
+    std::vector<double> cost;
+    for (int t = 0; t < n_tiles; ++t) {
+        tile_slot[t] = (int)per.size();
+        for (int k = 1; k <= s.max_order; ++k) {
+            const int a = s.order_start[k], b = s.order_start[k + 1];
+            if (b <= a) continue;
+            int chunk = (int)std::lround(item_exc * order_cost(2) / order_cost(k));
+            chunk = std::min(std::max(chunk, nslot), ITEM_MAX);
+            for (int u = a; u < b; u += chunk) {
+                WorkItem it{};
+                it.inst = 0;
+                it.spin = spin;
+                it.tile = t;
+                it.order = k;
+                it.u0 = u;
+                it.u1 = std::min(b, u + chunk);
+                it.slot = (int)per.size();
+                per.push_back(it);
+                cost.push_back(order_cost(k) * (it.u1 - it.u0));
+            }
+        }
+    }
+    tile_slot[n_tiles] = (int)per.size();
+    // scheduling order: most expensive first (the queue hands them out in order)
+    std::vector<int> idx(per.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    items.reserve(per.size());
+    for (int i : idx) items.push_back(per[i]);
+}
+
+// total order-2-equivalent cost of one walker tile of a spin
+static double tile_cost(const SpinHost &sp) {
+    double t = 0.0;
+    for (int k = 1; k <= sp.max_order; ++k)
+        t += order_cost(k) / order_cost(2) * (sp.order_start[k + 1] - sp.order_start[k]);
+    return t;
+}
+
+// excitations per work item so that the whole launch has about
+// `waves_of_items` rounds of blocks over the CUs (fewer, larger items mean
+// fewer re-stagings of the walker tile's table in LDS)
+static int item_size_for(const mde_ctx *c, const SpinHost &sp, int W, int WT, int threads,
+                         size_t lds) {
+    const int n_tiles = (W + WT - 1) / WT;
+    int per_cu = (int)std::min<size_t>(160 * 1024 / std::max<size_t>(lds, 1024), 2048 / threads);
+    per_cu = std::max(per_cu, 1);
+    const double target_items = 2.0 * c->n_cu * per_cu;
+    const double items_per_tile = std::max(1.0, target_items / n_tiles);
+    const int nslot = threads / WT;
+    const int sz = (int)std::ceil(tile_cost(sp) / items_per_tile);
+    return std::max(sz, 4 * nslot);
+}
+
+static Plan default_plan(const mde_ctx *c, int W) {
+    Plan p{};
+    const size_t esz = c->d.precision == 0 ? 8 : 4;
+    // largest walker tile whose tables fit in ~96 KB of LDS for both spins
+    int WT = 64;
+    for (int s = 0; s < 2; ++s) {
+        const SpinHost &sp = c->sp[s];
+        const size_t per_w = (size_t)(sp.n * sp.m + 4 * sp.m + sp.n) * esz;
+        int wt = 64;
+        while (wt > 1 && per_w * (wt + (wt >= 8 ? 1 : 0)) > 96 * 1024) wt /= 2;
+        WT = std::min(WT, wt);
+    }
+    WT = std::min(WT, std::max(1, pow2_floor(std::max(W, 1))));
+    p.WT = WT;
+    for (int s = 0; s < 2; ++s) {
+        p.threads[s] = (WT >= 16) ? 1024 : 256;
+        const size_t lds = det_lds(c->sp[s], WT, p.threads[s], c->d.precision, true);
+        p.item_exc[s] = item_size_for(c, c->sp[s], W, WT, p.threads[s], lds);
+    }
+    return p;
+}
+
+static std::vector<Plan> candidate_plans(const mde_ctx *c, int W) {
+    std::vector<Plan> out;
+    Plan d = default_plan(c, W);
+    out.push_back(d);
+    const int wts[3] = {d.WT, std::max(1, d.WT / 2), std::max(1, d.WT / 4)};
+    const int thr[3] = {256, 512, 1024};
+    const double scale[3] = {0.5, 1.0, 2.0};
+    for (int a = 0; a < 3; ++a) {
+        if (a > 0 && wts[a] == wts[a - 1]) continue;
+        for (int b = 0; b < 3; ++b) {
+            if (thr[b] < wts[a]) continue;
+            for (int e = 0; e < 3; ++e) {
+                Plan p{};
+                p.WT = wts[a];
+                for (int s = 0; s < 2; ++s) {
+                    p.threads[s] = thr[b];
+                    const size_t lds = det_lds(c->sp[s], p.WT, thr[b], c->d.precision, true);
+                    const int base = item_size_for(c, c->sp[s], W, p.WT, thr[b], lds);
+                    p.item_exc[s] = std::max((int)(base * scale[e]), 4 * (thr[b] / p.WT));
+                }
+                out.push_back(p);
+            }
+        }
+    }
+    return out;
+}
+
+// size the workspace for W walkers; assign pointers when base != nullptr
+static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullptr) {
+    Carver cv{base};
+    InstDev &h = c->h;
+    const int prec = c->d.precision;
+    const int nmax = std::max(c->sp[0].n, c->sp[1].n);
+    const int mmax = std::max(c->sp[0].m, c->sp[1].m);
+    const int nomax = std::max(c->sp[0].no, c->sp[1].no);
+    InstDev *d_inst = cv.take<InstDev>(1);
+    // plan-dependent sizes: the maximum over candidate plans
+    size_t max_items[2] = {0, 0}, max_partial[2] = {0, 0}, max_tiles[2] = {0, 0};
+    for (const Plan &p : candidate_plans(c, W)) {
+        for (int s = 0; s < 2; ++s) {
+            std::vector<WorkItem> it;
+            std::vector<int> ts;
+            build_items(c->sp[s], W, p.WT, p.item_exc[s], p.threads[s], it, ts, s);
+            max_items[s] = std::max(max_items[s], it.size());
+            max_partial[s] = std::max(max_partial[s], it.size() * (size_t)p.WT * NSUM);
+            max_tiles[s] = std::max(max_tiles[s], ts.size());
+        }
+    }
+    // current plan (set by the caller) may exceed candidates
+    for (int s = 0; s < 2; ++s) {
+        std::vector<WorkItem> it;
+        std::vector<int> ts;
+        build_items(c->sp[s], W, c->WT, c->sp[s].item_exc, c->sp[s].threads, it, ts, s);
+        max_items[s] = std::max(max_items[s], it.size());
+        max_partial[s] = std::max(max_partial[s], it.size() * (size_t)c->WT * NSUM);
+        max_tiles[s] = std::max(max_tiles[s], ts.size());
+    }
+    const size_t Wp = (size_t)W + 64;   // room for a partial last tile of any WT (tiled buffers)
+    for (int s = 0; s < 2; ++s) {
+        SpinHost &sp = c->sp[s];
+        SpinDev &S = h.s[s];
+        S.ex = cv.take<uint4>(sp.U);
+        S.ci_seg = cv.take<int32_t>(sp.U + 1);
+        S.ci_other = cv.take<int32_t>(c->n_det);
+        S.ci_idx = cv.take<int32_t>(c->n_det);
+        S.inv_off = cv.take<int32_t>((size_t)sp.n * sp.m + 1);
+        S.inv_ent = cv.take<int32_t>(sp.inv_ent.size());
+        int32_t *ts = cv.take<int32_t>(max_tiles[s]);
+        WorkItem *its = cv.take<WorkItem>(max_items[s]);
+        int32_t *pu = cv.take<int32_t>(sp.U);
+        S.Phi = cv.take<double>((size_t)W * sp.n * sp.no);
+        S.B = cv.take<double>((size_t)W * sp.n * sp.n);
+        S.T = prec == 0 ? cv.take<double>(Wp * sp.n * sp.m) : nullptr;
+        S.T32 = prec == 1 ? cv.take<float>(Wp * sp.n * sp.m) : nullptr;
+        S.PhiV32 = prec == 1 ? cv.take<float>((size_t)W * sp.n * sp.m) : nullptr;
+        S.logdet = cv.take<double>(W);
+        S.sgn = cv.take<double>(W);
+        S.R = cv.take<double>(Wp * sp.U);
+        S.C = cv.take<double>(Wp * sp.U);
+        S.partial = cv.take<double>(max_partial[s]);
+        S.coef_s = cv.take<double>(c->n_det);
+        S.chunks = cv.take<int32_t>(sp.chunks.size());
+        S.pieces = cv.take<int4>(sp.pieces.size());
+        S.longs = cv.take<int4>(sp.longs.size());
+        S.pc_part = cv.take<double>(sp.pieces.size() * Wp);
+        if (base) {
+            S.tile_slot = ts;
+            S.items = its;
+            c->d_tile_slot[s] = ts;
+            c->d_items[s] = its;
+            c->d_perm_user[s] = pu;
+            c->items_cap[s] = max_items[s];
+            c->partial_cap[s] = max_partial[s];
+            c->tileslot_cap[s] = max_tiles[s];
+        }
+        if (c->nb[s] > 0) {
+            double *cc = cv.take<double>((size_t)3 * c->nb[s]);
+            double *ee = cv.take<double>(c->nb[s]);
+            double *mm = cv.take<double>((size_t)sp.no * c->nb[s]);
+            if (base) {
+                c->d_centres[s] = cc;
+                c->d_expo[s] = ee;
+                c->d_mo[s] = mm;
+            }
+        }
+    }
+    h.coef = cv.take<double>(c->n_det);
+    h.Nold = cv.take<double>(W);
+    h.Nnew = cv.take<double>(W);
+    h.rho = cv.take<double>(W);
+    const size_t Wq = (size_t)W + 64;
+    h.cp = cv.take<double>(Wq * nmax);
+    h.Tp = prec == 0 ? cv.take<double>(Wq * nmax * mmax) : nullptr;
+    h.rhoA = cv.take<double>((size_t)W * 4);
+    h.g = prec == 0 ? cv.take<double>(Wq * 4 * mmax) : nullptr;
+    h.newrow = cv.take<double>((size_t)W * nomax);
+    h.g32 = prec == 1 ? cv.take<float>(Wq * 4 * mmax) : nullptr;
+    h.cp32 = prec == 1 ? cv.take<float>(Wq * nmax) : nullptr;
+    h.Tp32 = prec == 1 ? cv.take<float>(Wq * nmax * mmax) : nullptr;
+    h.Ap32 = prec == 1 ? cv.take<float>((size_t)W * (nmax + 4) * nmax) : nullptr;
+    h.st = cv.take<int32_t>(W);
+    h.counter = cv.take<int32_t>(64);
+    h.Lnew = cv.take<double>(W);
+    if (base) {
+        c->d_inst = d_inst;
+        h.W = W;
+        h.prec = prec;
+        h.nmax = nmax;
+        h.mmax = mmax;
+        h.nomax = nomax;
+        h.n_det = c->n_det;
+    }
+    if (max_items_out) *max_items_out = max_items[0] + max_items[1];
+    return cv.off;
+}
+
+// apply the context's plan: items, slots, LDS sizes, grids (host + upload)
+static mde_status apply_plan(mde_ctx *c) {
+    for (int s = 0; s < 2; ++s) {
+        SpinHost &sp = c->sp[s];
+        SpinDev &S = c->h.s[s];
+        std::vector<WorkItem> items;
+        std::vector<int> ts;
+        build_items(sp, c->W, c->WT, sp.item_exc, sp.threads, items, ts, s);
+        if (items.size() > c->items_cap[s] || items.size() * (size_t)c->WT * NSUM > c->partial_cap[s] ||
+            ts.size() > c->tileslot_cap[s])
+            MDE_FAIL(c, MDE_NOMEM, "plan needs more workspace than was sized (spin %d)", s);
+        sp.items = items;
+        sp.tile_slot = ts;
+        S.WT = c->WT;
+        S.WTP = (c->WT >= 8) ? c->WT + 1 : c->WT;
+        S.n_tiles = (c->W + c->WT - 1) / c->WT;
+        S.n_slots = (int)items.size();
+        sp.ex_cap = 16;
+        for (const WorkItem &it : items) sp.ex_cap = std::max(sp.ex_cap, it.u1 - it.u0);
+        sp.lds_prop = det_lds(sp, c->WT, sp.threads, c->d.precision, true, sp.ex_cap);
+        sp.lds_val = det_lds(sp, c->WT, sp.threads, c->d.precision, false, sp.ex_cap);
+        if (sp.lds_prop > 160 * 1024)
+            MDE_FAIL(c, MDE_UNSUPPORTED, "tables of spin %d need %zu bytes of LDS", s, sp.lds_prop);
+        const size_t lds = std::max<size_t>(sp.lds_prop, 1024);
+        int per_cu = (int)std::min<size_t>(160 * 1024 / lds, 2048 / sp.threads);
+        per_cu = std::max(per_cu, 1);
+        sp.grid = (int)std::min<size_t>(items.size(), (size_t)c->n_cu * per_cu);
+        sp.grid = std::max(sp.grid, 1);
+        if (!items.empty()) {
+            MDE_HIP(c, hipMemcpy(c->d_items[s], items.data(), sizeof(WorkItem) * items.size(),
+                                 hipMemcpyHostToDevice));
+        }
+        MDE_HIP(c, hipMemcpy(c->d_tile_slot[s], ts.data(), sizeof(int) * ts.size(),
+                             hipMemcpyHostToDevice));
+    }
+    MDE_HIP(c, hipMemcpy(c->d_inst, &c->h, sizeof(InstDev), hipMemcpyHostToDevice));
+    c->R_valid[0] = c->R_valid[1] = false;
+    c->C_valid[0] = c->C_valid[1] = false;
+    return MDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// state maintenance
+// ---------------------------------------------------------------------------
+
+static MoveArgs no_move() {
+    MoveArgs m{};
+    m.spin = -1;
+    return m;
+}
+
+static mde_status run_values(mde_ctx *c, int s, const double *tab0 = nullptr,
+                             const double *tab1 = nullptr) {
+    SpinHost &sp = c->sp[s];
+    if (sp.items.empty()) {
+        c->R_valid[s] = true;
+        return MDE_OK;
+    }
+    MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], (int)sp.items.size(), sp.ex_cap,
+                          nullptr, no_move(), DM_VALUES, c->d.precision, c->WT,
+                          std::max<size_t>(sp.lds_val, 16), sp.threads, sp.grid, c->h.counter,
+                          tab0, tab1));
+    c->R_valid[s] = true;
+    return MDE_OK;
+}
+
+static mde_status ensure_C(mde_ctx *c, int s) {
+    if (c->C_valid[s]) return MDE_OK;
+    if (!c->R_valid[1 - s]) {
+        mde_status st = run_values(c, 1 - s);
+        if (st) return st;
+    }
+    MDE_HIP(c, launch_precontract(c->stream, c->d_inst, c->h, s, c->h.coef));
+    c->C_valid[s] = true;
+    return MDE_OK;
+}
+
+// from-scratch evaluation; orb_* NULL means "use the kept orbital values"
+static mde_status full_eval(mde_ctx *c, const double *orb_up, const double *orb_dn,
+                            double *log_abs, double *sign, int32_t *status) {
+    const double *orb[2] = {orb_up, orb_dn};
+    MDE_HIP(c, launch_coef_gather(c->stream, c->d_inst, c->h, c->h.coef));
+    for (int s = 0; s < 2; ++s) {
+        MDE_HIP(c, launch_lu_inverse(c->stream, c->d_inst, c->h, s, orb[s], status));
+        MDE_HIP(c, launch_table_gemm(c->stream, c->d_inst, c->h, s));
+    }
+    c->R_valid[0] = c->R_valid[1] = false;
+    c->C_valid[0] = c->C_valid[1] = false;
+    for (int s = 0; s < 2; ++s) {
+        mde_status st = run_values(c, s);
+        if (st) return st;
+    }
+    // N = sum_u C_up[u] R_up[u] needs the up weights; the down weights are
+    // formed when a down electron next moves
+    mde_status st0 = ensure_C(c, 0);
+    if (st0) return st0;
+    MDE_HIP(c, launch_nsum(c->stream, c->d_inst, c->h, log_abs, sign, status, 1));
+    c->initialized = true;
+    c->adjoint_state = false;
+    c->pending_e = -1;
+    return MDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *mde_version(void) { return kVersion; }
+
+const char *mde_error_string(const mde_ctx *ctx) {
+    if (!ctx) return "no context";
+    return ctx->err.c_str();
+}
+
+mde_status mde_create(const mde_desc *desc, void *hip_stream, mde_ctx **out) {
+    if (!desc || !out) return MDE_INVALID;
+    *out = nullptr;
+    for (int s = 0; s < 2; ++s) {
+        if (desc->n_elec[s] < 1 || desc->n_elec[s] > MDE_MAX_ELEC) return MDE_UNSUPPORTED;
+        const int m = desc->n_orb[s] - desc->n_elec[s];
+        if (m < 1 || m > MDE_MAX_VIRT) return MDE_UNSUPPORTED;
+    }
+    if (desc->max_walkers < 1 || desc->max_order < 1 || desc->max_order > MDE_MAX_ORDER)
+        return MDE_INVALID;
+    if (desc->precision != MDE_FP64 && desc->precision != MDE_MIXED) return MDE_INVALID;
+    mde_ctx *c = new (std::nothrow) mde_ctx();
+    if (!c) return MDE_NOMEM;
+    c->d = *desc;
+    if (c->d.refresh_every < 0) c->d.refresh_every = 0;
+    c->stream = (hipStream_t)hip_stream;
+    for (int s = 0; s < 2; ++s) {
+        c->sp[s].n = desc->n_elec[s];
+        c->sp[s].no = desc->n_orb[s];
+        c->sp[s].m = desc->n_orb[s] - desc->n_elec[s];
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        c->n_cu = std::max(1, prop.multiProcessorCount);
+    *out = c;
+    return MDE_OK;
+}
+
+mde_status mde_destroy(mde_ctx *ctx) {
+    delete ctx;
+    return MDE_OK;
+}
+
+mde_status mde_set_excitations(mde_ctx *c, int32_t spin, int32_t n_exc, const int32_t *offsets,
+                               const int32_t *holes, const int32_t *particles) {
+    if (!c) return MDE_INVALID;
+    if (c->bound) MDE_FAIL(c, MDE_STATE, "expansion is fixed once the workspace is bound");
+    if (spin < 0 || spin > 1) MDE_FAIL(c, MDE_INVALID, "spin must be 0 or 1");
+    if (n_exc < 1 || !offsets) MDE_FAIL(c, MDE_INVALID, "need at least the reference excitation");
+    SpinHost &sp = c->sp[spin];
+    const int n = sp.n, no = sp.no;
+    if (offsets[0] != 0 || offsets[1] != 0) MDE_FAIL(c, MDE_INVALID, "excitation 0 must be empty");
+    struct Key {
+        int k;
+        std::vector<int> h, p;
+        int user;
+    };
+    std::vector<Key> keys((size_t)n_exc);
+    int max_order = 0;
+    for (int u = 0; u < n_exc; ++u) {
+        const int a = offsets[u], b = offsets[u + 1];
+        const int k = b - a;
+        if (k < 0 || k > c->d.max_order || k > n)
+            MDE_FAIL(c, MDE_INVALID, "excitation %d has order %d (max_order %d)", u, k, c->d.max_order);
+        if (u > 0 && k == 0) MDE_FAIL(c, MDE_INVALID, "excitation %d is empty (only 0 may be)", u);
+        Key &K = keys[u];
+        K.k = k;
+        K.user = u;
+        for (int t = a; t < b; ++t) {
+            if (holes[t] < 0 || holes[t] >= n)
+                MDE_FAIL(c, MDE_INVALID, "excitation %d: hole %d out of range", u, holes[t]);
+            if (particles[t] < n || particles[t] >= no)
+                MDE_FAIL(c, MDE_INVALID, "excitation %d: particle %d out of range", u, particles[t]);
+            if (t > a && (holes[t] <= holes[t - 1] || particles[t] <= particles[t - 1]))
+                MDE_FAIL(c, MDE_INVALID, "excitation %d: holes/particles must ascend", u);
+            K.h.push_back(holes[t]);
+            K.p.push_back(particles[t] - n);
+        }
+        max_order = std::max(max_order, k);
+    }
+    std::vector<int> order((size_t)n_exc);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin() + 1, order.end(), [&](int x, int y) {
+        const Key &a = keys[x], &b = keys[y];
+        if (a.k != b.k) return a.k < b.k;
+        if (a.h != b.h) return a.h < b.h;
+        return a.p < b.p;
+    });
+    for (int i = 1; i < n_exc; ++i) {
+        const Key &a = keys[order[i - 1]], &b = keys[order[i]];
+        if (a.k == b.k && a.h == b.h && a.p == b.p)
+            MDE_FAIL(c, MDE_INVALID, "excitations %d and %d are the same", a.user, b.user);
+    }
+    sp.U = n_exc;
+    sp.max_order = max_order;
+    sp.perm = order;
+    sp.iperm.assign(n_exc, 0);
+    for (int i = 0; i < n_exc; ++i) sp.iperm[order[i]] = i;
+    sp.ex.assign(n_exc, uint4{0, 0, 0, 0});
+    sp.orders.assign(n_exc, 0);
+    for (int i = 0; i < n_exc; ++i) {
+        const Key &K = keys[order[i]];
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int j = 0; j < K.k; ++j) {
+            w[j >> 2] |= (uint32_t)K.h[j] << ((j & 3) * 8);
+            w[2 + (j >> 2)] |= (uint32_t)K.p[j] << ((j & 3) * 8);
+        }
+        sp.ex[i] = uint4{w[0], w[1], w[2], w[3]};
+        sp.orders[i] = K.k;
+    }
+    for (int k = 0; k <= MAXK + 1; ++k) sp.order_start[k] = n_exc;
+    for (int i = n_exc - 1; i >= 0; --i) sp.order_start[sp.orders[i]] = i;
+    for (int k = MAXK; k >= 0; --k) sp.order_start[k] = std::min(sp.order_start[k], sp.order_start[k + 1]);
+    // inverted index (entry (h, p) -> (u, j, l))
+    const int nm = n * sp.m;
+    std::vector<int> cnt(nm + 1, 0);
+    for (int i = 0; i < n_exc; ++i) {
+        const Key &K = keys[order[i]];
+        for (int j = 0; j < K.k; ++j)
+            for (int l = 0; l < K.k; ++l) cnt[K.h[j] * sp.m + K.p[l] + 1]++;
+    }
+    for (int e = 0; e < nm; ++e) cnt[e + 1] += cnt[e];
+    sp.inv_off = cnt;
+    sp.inv_ent.assign(cnt[nm], 0);
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < n_exc; ++i) {
+        const Key &K = keys[order[i]];
+        for (int j = 0; j < K.k; ++j)
+            for (int l = 0; l < K.k; ++l)
+                sp.inv_ent[pos[K.h[j] * sp.m + K.p[l]]++] = (i << 10) | (K.k << 6) | (j << 3) | l;
+    }
+    if (n_exc >= (1 << 21)) MDE_FAIL(c, MDE_UNSUPPORTED, "too many excitations");
+    sp.have = true;
+    c->have_ci = false;
+    return MDE_OK;
+}
+
+mde_status mde_set_ci(mde_ctx *c, int64_t n_det, const double *coef, const int32_t *up_idx,
+                      const int32_t *dn_idx) {
+    if (!c) return MDE_INVALID;
+    if (c->bound) MDE_FAIL(c, MDE_STATE, "expansion is fixed once the workspace is bound");
+    if (!c->sp[0].have || !c->sp[1].have) MDE_FAIL(c, MDE_STATE, "set both excitation lists first");
+    if (n_det < 1 || n_det > (int64_t)1 << 30) MDE_FAIL(c, MDE_INVALID, "bad n_det");
+    const int *idx[2] = {up_idx, dn_idx};
+    for (int64_t I = 0; I < n_det; ++I)
+        for (int s = 0; s < 2; ++s)
+            if (idx[s][I] < 0 || idx[s][I] >= c->sp[s].U)
+                MDE_FAIL(c, MDE_INVALID, "determinant %lld: excitation index out of range", (long long)I);
+    c->n_det = n_det;
+    c->coef.assign(coef, coef + n_det);
+    c->up_idx.assign(up_idx, up_idx + n_det);
+    c->dn_idx.assign(dn_idx, dn_idx + n_det);
+    for (int s = 0; s < 2; ++s) {
+        SpinHost &sp = c->sp[s];
+        std::vector<int> cnt(sp.U + 1, 0);
+        for (int64_t I = 0; I < n_det; ++I) cnt[sp.iperm[idx[s][I]] + 1]++;
+        for (int u = 0; u < sp.U; ++u) cnt[u + 1] += cnt[u];
+        sp.ci_seg = cnt;
+        sp.ci_other.assign(n_det, 0);
+        sp.ci_idx.assign(n_det, 0);
+        std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+        for (int64_t I = 0; I < n_det; ++I) {
+            const int u = sp.iperm[idx[s][I]];
+            const int k = pos[u]++;
+            sp.ci_other[k] = c->sp[1 - s].iperm[idx[1 - s][I]];
+            sp.ci_idx[k] = (int)I;
+        }
+        // precontraction work units: chunks of consecutive excitations with
+        // short CI segments (about 64 terms each) and 64-term pieces of the
+        // long segments
+        const int PIECE = 64;
+        sp.chunks.assign(1, 0);
+        sp.pieces.clear();
+        sp.longs.clear();
+        std::vector<int> starts, ends;
+        int acc = 0, cur = 0;
+        for (int u = 0; u < sp.U; ++u) {
+            const int len = sp.ci_seg[u + 1] - sp.ci_seg[u];
+            if (len > PIECE) {
+                if (u > cur) { starts.push_back(cur); ends.push_back(u); }
+                const int pb = (int)sp.pieces.size();
+                for (int k = sp.ci_seg[u]; k < sp.ci_seg[u + 1]; k += PIECE)
+                    sp.pieces.push_back(int4{u, k, std::min(k + PIECE, sp.ci_seg[u + 1]), 0});
+                sp.longs.push_back(int4{u, pb, (int)sp.pieces.size(), 0});
+                cur = u + 1;
+                acc = 0;
+                continue;
+            }
+            acc += len;
+            if (acc >= PIECE) {
+                starts.push_back(cur);
+                ends.push_back(u + 1);
+                cur = u + 1;
+                acc = 0;
+            }
+        }
+        if (cur < sp.U) { starts.push_back(cur); ends.push_back(sp.U); }
+        // chunks as (start, end) pairs flattened: chunks[2c], chunks[2c+1]
+        sp.chunks.clear();
+        for (size_t i = 0; i < starts.size(); ++i) {
+            sp.chunks.push_back(starts[i]);
+            sp.chunks.push_back(ends[i]);
+        }
+        if (sp.chunks.empty()) { sp.chunks.push_back(0); sp.chunks.push_back(0); }
+    }
+    c->have_ci = true;
+    // default plan
+    Plan p = default_plan(c, c->d.max_walkers);
+    c->WT = p.WT;
+    for (int s = 0; s < 2; ++s) {
+        c->sp[s].threads = p.threads[s];
+        c->sp[s].item_exc = p.item_exc[s];
+    }
+    return MDE_OK;
+}
+
+mde_status mde_sgauss_set_basis(mde_ctx *c, int32_t spin, int32_t nb, const double *centres,
+                                const double *expo, const double *mo) {
+    if (!c) return MDE_INVALID;
+    if (c->bound) MDE_FAIL(c, MDE_STATE, "set the basis before binding the workspace");
+    if (spin < 0 || spin > 1 || nb < 1 || nb > 3072) MDE_FAIL(c, MDE_INVALID, "bad basis (1..3072 functions)");
+    c->nb[spin] = nb;
+    c->centres[spin].assign(centres, centres + 3 * (size_t)nb);
+    c->expo[spin].assign(expo, expo + nb);
+    c->mo[spin].assign(mo, mo + (size_t)c->sp[spin].no * nb);
+    return MDE_OK;
+}
+
+mde_status mde_workspace_bytes(const mde_ctx *cc, int32_t W, size_t *bytes) {
+    mde_ctx *c = const_cast<mde_ctx *>(cc);
+    if (!c || !bytes) return MDE_INVALID;
+    if (!c->have_ci) MDE_FAIL(c, MDE_STATE, "set excitations and CI first");
+    if (W < 1 || W > c->d.max_walkers) MDE_FAIL(c, MDE_INVALID, "W out of range");
+    Plan p = default_plan(c, W);
+    if (!c->bound) {
+        c->WT = p.WT;
+        for (int s = 0; s < 2; ++s) {
+            c->sp[s].threads = p.threads[s];
+            c->sp[s].item_exc = p.item_exc[s];
+        }
+    }
+    *bytes = carve(c, W, nullptr) + 256;
+    return MDE_OK;
+}
+
+mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
+    if (!c || !dev) return MDE_INVALID;
+    if (c->bound) MDE_FAIL(c, MDE_STATE, "workspace already bound");
+    if (!c->have_ci) MDE_FAIL(c, MDE_STATE, "set excitations and CI first");
+    if (W < 1 || W > c->d.max_walkers) MDE_FAIL(c, MDE_INVALID, "W out of range");
+    if (((uintptr_t)dev) % 256) MDE_FAIL(c, MDE_INVALID, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    Plan p = default_plan(c, W);
+    c->WT = p.WT;
+    for (int s = 0; s < 2; ++s) {
+        c->sp[s].threads = p.threads[s];
+        c->sp[s].item_exc = p.item_exc[s];
+    }
+    need = carve(c, W, nullptr);
+    if (bytes < need) MDE_FAIL(c, MDE_NOMEM, "workspace has %zu bytes, needs %zu", bytes, need);
+    c->W = W;
+    c->ws = (char *)dev;
+    c->ws_bytes = bytes;
+    carve(c, W, c->ws);
+    // upload the expansion
+    for (int s = 0; s < 2; ++s) {
+        SpinHost &sp = c->sp[s];
+        SpinDev &S = c->h.s[s];
+        S.n = sp.n;
+        S.m = sp.m;
+        S.no = sp.no;
+        S.U = sp.U;
+        S.max_order = sp.max_order;
+        for (int k = 0; k < MAXK + 2; ++k) S.order_start[k] = sp.order_start[k];
+        MDE_HIP(c, hipMemcpy((void *)S.ex, sp.ex.data(), sizeof(uint4) * sp.U, hipMemcpyHostToDevice));
+        MDE_HIP(c, hipMemcpy((void *)S.ci_seg, sp.ci_seg.data(), sizeof(int) * (sp.U + 1),
+                             hipMemcpyHostToDevice));
+        MDE_HIP(c, hipMemcpy((void *)S.ci_other, sp.ci_other.data(), sizeof(int) * c->n_det,
+                             hipMemcpyHostToDevice));
+        MDE_HIP(c, hipMemcpy((void *)S.ci_idx, sp.ci_idx.data(), sizeof(int) * c->n_det,
+                             hipMemcpyHostToDevice));
+        MDE_HIP(c, hipMemcpy((void *)S.chunks, sp.chunks.data(), sizeof(int) * sp.chunks.size(),
+                             hipMemcpyHostToDevice));
+        if (!sp.pieces.empty()) {
+            MDE_HIP(c, hipMemcpy((void *)S.pieces, sp.pieces.data(), sizeof(int4) * sp.pieces.size(),
+                                 hipMemcpyHostToDevice));
+            MDE_HIP(c, hipMemcpy((void *)S.longs, sp.longs.data(), sizeof(int4) * sp.longs.size(),
+                                 hipMemcpyHostToDevice));
+        }
+        S.n_chunks = (int)sp.chunks.size() / 2;
+        S.n_pieces = (int)sp.pieces.size();
+        S.n_longs = (int)sp.longs.size();
+        MDE_HIP(c, hipMemcpy((void *)S.inv_off, sp.inv_off.data(), sizeof(int) * sp.inv_off.size(),
+                             hipMemcpyHostToDevice));
+        if (!sp.inv_ent.empty())
+            MDE_HIP(c, hipMemcpy((void *)S.inv_ent, sp.inv_ent.data(),
+                                 sizeof(int) * sp.inv_ent.size(), hipMemcpyHostToDevice));
+        MDE_HIP(c, hipMemcpy(c->d_perm_user[s], sp.iperm.data(), sizeof(int) * sp.U,
+                             hipMemcpyHostToDevice));
+        if (c->nb[s] > 0) {
+            MDE_HIP(c, hipMemcpy(c->d_centres[s], c->centres[s].data(),
+                                 sizeof(double) * c->centres[s].size(), hipMemcpyHostToDevice));
+            MDE_HIP(c, hipMemcpy(c->d_expo[s], c->expo[s].data(), sizeof(double) * c->expo[s].size(),
+                                 hipMemcpyHostToDevice));
+            MDE_HIP(c, hipMemcpy(c->d_mo[s], c->mo[s].data(), sizeof(double) * c->mo[s].size(),
+                                 hipMemcpyHostToDevice));
+        }
+    }
+    MDE_HIP(c, hipMemcpy((void *)c->h.coef, c->coef.data(), sizeof(double) * c->n_det,
+                         hipMemcpyHostToDevice));
+    c->bound = true;
+    mde_status st = apply_plan(c);
+    if (st) return st;
+    MDE_HIP(c, launch_init_misc(c->stream, c->d_inst, c->h));
+    MDE_HIP(c, hipStreamSynchronize(c->stream));
+    return MDE_OK;
+}
+
+mde_status mde_init(mde_ctx *c, const double *orb_up, const double *orb_dn, double *log_abs_psi,
+                    double *sign_psi, int32_t *status) {
+    if (!c) return MDE_INVALID;
+    if (!c->bound) MDE_FAIL(c, MDE_STATE, "bind a workspace first");
+    if (!orb_up || !orb_dn) MDE_FAIL(c, MDE_INVALID, "orbital blocks required");
+    MDE_HIP(c, launch_fill_i32(c->stream, c->h.st, 0, c->W));
+    c->accept_count = 0;
+    return full_eval(c, orb_up, orb_dn, log_abs_psi, sign_psi, status);
+}
+
+mde_status mde_refresh(mde_ctx *c, double *log_abs_psi, double *sign_psi, int32_t *status) {
+    if (!c) return MDE_INVALID;
+    if (!c->initialized) MDE_FAIL(c, MDE_STATE, "call mde_init first");
+    return full_eval(c, nullptr, nullptr, log_abs_psi, sign_psi, status);
+}
+
+static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *ratio, double *grad,
+                             double *lap, int32_t *status) {
+    if (!c) return MDE_INVALID;
+    if (!c->initialized || c->adjoint_state) MDE_FAIL(c, MDE_STATE, "call mde_init/mde_refresh first");
+    if (e < 0 || e >= c->d.n_elec[0] + c->d.n_elec[1]) MDE_FAIL(c, MDE_INVALID, "electron out of range");
+    if (!orb) MDE_FAIL(c, MDE_INVALID, "orbital block required");
+    int row;
+    const int s = spin_of(c, e, &row);
+    mde_status st = ensure_C(c, s);
+    if (st) return st;
+    MoveArgs m{};
+    m.e = e;
+    m.spin = s;
+    m.row = row;
+    m.new_orb = orb;
+    m.ratio = ratio;
+    m.grad = grad;
+    m.lap = lap;
+    m.status = status;
+    const int nmax = c->h.nmax, mmax = c->h.mmax;
+    MDE_HIP(c, launch_propose(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, nmax, mmax,
+                              c->WT, c->h.s[s].n_tiles));
+    SpinHost &sp = c->sp[s];
+    if (!sp.items.empty())
+        MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], (int)sp.items.size(), sp.ex_cap,
+                              nullptr, m, DM_PROPOSE, c->d.precision, c->WT, sp.lds_prop, sp.threads,
+                              sp.grid, c->h.counter, nullptr, nullptr));
+    MDE_HIP(c, launch_finish(c->stream, c->d_inst, 1, c->W, nullptr, m, c->h.counter));
+    c->pending_e = e;
+    return MDE_OK;
+}
+
+mde_status mde_propose(mde_ctx *c, int32_t e, const double *new_orb, double *ratio, double *grad,
+                       double *lap, int32_t *status) {
+    return do_propose(c, e, new_orb, ratio, grad, lap, status);
+}
+
+mde_status mde_grad_lap(mde_ctx *c, int32_t e, const double *cur_orb, double *grad, double *lap,
+                        int32_t *status) {
+    return do_propose(c, e, cur_orb, nullptr, grad, lap, status);
+}
+
+mde_status mde_accept(mde_ctx *c, int32_t e, const uint8_t *accept) {
+    if (!c) return MDE_INVALID;
+    if (!c->initialized || c->adjoint_state) MDE_FAIL(c, MDE_STATE, "call mde_init first");
+    if (c->pending_e != e) MDE_FAIL(c, MDE_STATE, "no pending proposal for electron %d", e);
+    if (!accept) MDE_FAIL(c, MDE_INVALID, "accept mask required");
+    int row;
+    const int s = spin_of(c, e, &row);
+    MoveArgs m{};
+    m.e = e;
+    m.spin = s;
+    m.row = row;
+    m.accept = accept;
+    MDE_HIP(c, launch_accept(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, c->h.nmax,
+                             c->h.mmax, c->WT, c->h.s[s].n_tiles));
+    c->R_valid[s] = false;
+    c->C_valid[1 - s] = false;
+    c->pending_e = -1;
+    c->accept_count++;
+    if (c->d.refresh_every > 0 && c->accept_count % c->d.refresh_every == 0)
+        return full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr);
+    return MDE_OK;
+}
+
+mde_status mde_export(mde_ctx *c, int32_t what, int32_t spin, double *dst) {
+    if (!c || !dst) return MDE_INVALID;
+    if (!c->initialized) MDE_FAIL(c, MDE_STATE, "nothing to export yet");
+    if (spin < 0 || spin > 1 || what < 0 || what > 4) MDE_FAIL(c, MDE_INVALID, "bad export request");
+    if (what == 2 && !c->R_valid[spin]) {
+        mde_status st = run_values(c, spin);
+        if (st) return st;
+    }
+    MDE_HIP(c, launch_export(c->stream, c->d_inst, c->h, what, spin, dst, c->d_perm_user[spin]));
+    return MDE_OK;
+}
+
+mde_status mde_eval_tables(mde_ctx *c, const double *T_up, const double *T_dn, const double *coef,
+                           double *log_abs, double *sign, int32_t *status) {
+    if (!c) return MDE_INVALID;
+    if (!c->bound) MDE_FAIL(c, MDE_STATE, "bind a workspace first");
+    if (c->d.precision != MDE_FP64) MDE_FAIL(c, MDE_UNSUPPORTED, "the adjoint path is FP64");
+    if (!T_up || !T_dn || !coef) MDE_FAIL(c, MDE_INVALID, "tables and coefficients required");
+    MDE_HIP(c, launch_fill_i32(c->stream, c->h.st, 0, c->W));
+    MDE_HIP(c, launch_coef_gather(c->stream, c->d_inst, c->h, coef));
+    mde_status st = run_values(c, 0, T_up, T_dn);
+    if (st) return st;
+    st = run_values(c, 1, T_up, T_dn);
+    if (st) return st;
+    for (int s = 0; s < 2; ++s)
+        MDE_HIP(c, launch_precontract(c->stream, c->d_inst, c->h, s, coef));
+    MDE_HIP(c, launch_nsum(c->stream, c->d_inst, c->h, log_abs, sign, status, 0));
+    // the context's move state is now that of the explicit tables
+    c->last_T[0] = T_up;
+    c->last_T[1] = T_dn;
+    c->adjoint_state = true;
+    c->R_valid[0] = c->R_valid[1] = true;
+    c->C_valid[0] = c->C_valid[1] = true;
+    c->pending_e = -1;
+    return MDE_OK;
+}
+
+mde_status mde_backward(mde_ctx *c, const double *go, double *grad_coef, double *grad_T_up,
+                        double *grad_T_dn) {
+    if (!c) return MDE_INVALID;
+    if (!c->adjoint_state) MDE_FAIL(c, MDE_STATE, "call mde_eval_tables first");
+    if (!go) MDE_FAIL(c, MDE_INVALID, "upstream gradient required");
+    // the cofactors are taken from the tables given to mde_eval_tables; the
+    // caller keeps those buffers unchanged until this call
+    MDE_HIP(c, launch_backward(c->stream, c->d_inst, c->h, go, nullptr, nullptr, grad_coef,
+                               grad_T_up, grad_T_dn, c->last_T[0], c->last_T[1]));
+    return MDE_OK;
+}
+
+
+mde_status mde_set_plan(mde_ctx *c, int32_t spin, int32_t walker_tile, int32_t item_exc,
+                        int32_t threads) {
+    if (!c) return MDE_INVALID;
+    if (spin < 0 || spin > 1) MDE_FAIL(c, MDE_INVALID, "spin must be 0 or 1");
+    if (c->capturing) MDE_FAIL(c, MDE_STATE, "cannot re-plan during capture");
+    if (walker_tile) {
+        if (walker_tile < 1 || walker_tile > 64 || (walker_tile & (walker_tile - 1)))
+            MDE_FAIL(c, MDE_INVALID, "walker tile must be a power of two in 1..64");
+        c->WT = walker_tile;
+    }
+    if (threads) {
+        if (threads < 64 || threads > 1024 || threads % 64) MDE_FAIL(c, MDE_INVALID, "bad thread count");
+        c->sp[spin].threads = threads;
+    }
+    if (item_exc) {
+        if (item_exc < 1) MDE_FAIL(c, MDE_INVALID, "bad item size");
+        c->sp[spin].item_exc = item_exc;
+    }
+    for (int s = 0; s < 2; ++s)
+        if (c->sp[s].threads < c->WT) c->sp[s].threads = std::max(64, c->WT);
+    if (!c->bound) return MDE_OK;
+    mde_status st = apply_plan(c);
+    if (st) return st;
+    c->initialized = false;   // R and C layouts depend on the tile: re-init needed
+    MDE_HIP(c, launch_init_misc(c->stream, c->d_inst, c->h));
+    return MDE_OK;
+}
+
+mde_status mde_get_plan(const mde_ctx *c, int32_t spin, int32_t *walker_tile, int32_t *item_exc,
+                        int32_t *threads) {
+    if (!c || spin < 0 || spin > 1) return MDE_INVALID;
+    if (walker_tile) *walker_tile = c->WT;
+    if (item_exc) *item_exc = c->sp[spin].item_exc;
+    if (threads) *threads = c->sp[spin].threads;
+    return MDE_OK;
+}
+
+// internal re-plan that keeps the state valid (values + C + N recomputed
+// from the kept orbitals)
+static mde_status replan_keep_state(mde_ctx *c, const Plan &p) {
+    c->WT = p.WT;
+    for (int s = 0; s < 2; ++s) {
+        c->sp[s].threads = std::max(p.threads[s], std::max(64, p.WT));
+        c->sp[s].item_exc = p.item_exc[s];
+    }
+    mde_status st = apply_plan(c);
+    if (st) return st;
+    MDE_HIP(c, launch_init_misc(c->stream, c->d_inst, c->h));
+    return full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+static std::string shape_key(const mde_ctx *c) {
+    std::ostringstream o;
+    o << "v1 prec=" << c->d.precision << " W=" << c->W;
+    for (int s = 0; s < 2; ++s) {
+        const SpinHost &sp = c->sp[s];
+        o << " s" << s << ":n=" << sp.n << ",m=" << sp.m << ",U=" << sp.U << ",k=";
+        for (int k = 1; k <= sp.max_order; ++k)
+            o << (sp.order_start[k + 1] - sp.order_start[k]) << (k < sp.max_order ? "/" : "");
+    }
+    o << " ndet=" << c->n_det;
+    return o.str();
+}
+
+mde_status mde_autotune(mde_ctx *c, const double *new_orb_up, const double *new_orb_dn,
+                        const char *cache_path) {
+    if (!c) return MDE_INVALID;
+    if (!c->initialized || c->adjoint_state) MDE_FAIL(c, MDE_STATE, "call mde_init first");
+    if (c->capturing) MDE_FAIL(c, MDE_STATE, "cannot tune during capture");
+    const std::string key = shape_key(c);
+    if (cache_path) {
+        std::ifstream f(cache_path);
+        std::string line;
+        while (std::getline(f, line)) {
+            const size_t bar = line.find(" | ");
+            if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+            Plan p{};
+            if (sscanf(line.c_str() + bar + 3, "%d %d %d %d %d", &p.WT, &p.item_exc[0], &p.threads[0],
+                       &p.item_exc[1], &p.threads[1]) == 5)
+                return replan_keep_state(c, p);
+        }
+    }
+    const double *orb[2] = {new_orb_up, new_orb_dn};
+    const int e_of[2] = {0, c->d.n_elec[0]};
+    hipEvent_t e0, e1;
+    MDE_HIP(c, hipEventCreate(&e0));
+    MDE_HIP(c, hipEventCreate(&e1));
+    double best_t = 1e30;
+    Plan best = default_plan(c, c->W);
+    best.WT = c->WT;
+    for (int s = 0; s < 2; ++s) {
+        best.item_exc[s] = c->sp[s].item_exc;
+        best.threads[s] = c->sp[s].threads;
+    }
+    std::vector<Plan> cands = candidate_plans(c, c->W);
+    cands.insert(cands.begin(), best);
+    for (const Plan &p : cands) {
+        mde_status st = replan_keep_state(c, p);
+        if (st) {
+            c->err.clear();
+            continue;
+        }
+        // one warm proposal per spin, then timed: 3 proposals per spin
+        double total = 0.0;
+        bool ok = true;
+        for (int s = 0; s < 2 && ok; ++s) {
+            if (!orb[s]) continue;
+            if (do_propose(c, e_of[s], orb[s], nullptr, nullptr, nullptr, nullptr)) { ok = false; break; }
+            MDE_HIP(c, hipEventRecord(e0, c->stream));
+            for (int r = 0; r < 3; ++r)
+                if (do_propose(c, e_of[s], orb[s], nullptr, nullptr, nullptr, nullptr)) ok = false;
+            MDE_HIP(c, hipEventRecord(e1, c->stream));
+            MDE_HIP(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            MDE_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+        }
+        if (ok && total < best_t) {
+            best_t = total;
+            best = p;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    mde_status st = replan_keep_state(c, best);
+    if (st) return st;
+    c->pending_e = -1;
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        f << key << " | " << best.WT << " " << best.item_exc[0] << " " << best.threads[0] << " "
+          << best.item_exc[1] << " " << best.threads[1] << "\n";
+    }
+    return MDE_OK;
+}
+
+// ---- graphs -----------------------------------------------------------------
+
+mde_status mde_capture_begin(mde_ctx *c) {
+    if (!c) return MDE_INVALID;
+    if (c->capturing) MDE_FAIL(c, MDE_STATE, "already capturing");
+    MDE_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    return MDE_OK;
+}
+
+mde_status mde_capture_end(mde_ctx *c, mde_graph **out) {
+    if (!c || !out) return MDE_INVALID;
+    if (!c->capturing) MDE_FAIL(c, MDE_STATE, "not capturing");
+    c->capturing = false;
+    mde_graph *g = new (std::nothrow) mde_graph();
+    if (!g) return MDE_NOMEM;
+    hipError_t e = hipStreamEndCapture(c->stream, &g->graph);
+    if (e != hipSuccess) {
+        delete g;
+        MDE_FAIL(c, MDE_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g->graph);
+        delete g;
+        MDE_FAIL(c, MDE_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return MDE_OK;
+}
+
+mde_status mde_graph_launch(mde_graph *g, void *hip_stream) {
+    if (!g) return MDE_INVALID;
+    return hipGraphLaunch(g->exec, (hipStream_t)hip_stream) == hipSuccess ? MDE_OK : MDE_DEVICE;
+}
+
+mde_status mde_graph_destroy(mde_graph *g) {
+    if (!g) return MDE_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (void *p : g->host_bufs) (void)hipHostFree(p);
+    delete g;
+    return MDE_OK;
+}
+
+// ---- s-Gaussian provider ------------------------------------------------------
+
+mde_status mde_sgauss_eval(mde_ctx *c, int32_t spin, int32_t npos, const double *pos, double *out) {
+    if (!c) return MDE_INVALID;
+    if (!c->bound) MDE_FAIL(c, MDE_STATE, "bind a workspace first");
+    if (spin < 0 || spin > 1 || c->nb[spin] == 0) MDE_FAIL(c, MDE_STATE, "no basis for this spin");
+    if (npos < 0 || (npos > 0 && (!pos || !out))) MDE_FAIL(c, MDE_INVALID, "bad positions");
+    MDE_HIP(c, launch_sgauss(c->stream, c->nb[spin], c->d_centres[spin], c->d_expo[spin],
+                             c->sp[spin].no, c->d_mo[spin], npos, pos, out));
+    return MDE_OK;
+}
+
+// ---- uneven batch --------------------------------------------------------------
+
+#define MDE_GFAIL(g, code, ...)                                  \
+    do {                                                         \
+        char _b[512];                                            \
+        snprintf(_b, sizeof(_b), __VA_ARGS__);                   \
+        if (g) (g)->err = _b;                                    \
+        return code;                                             \
+    } while (0)
+
+static size_t group_items(mde_ctx *const *ctxs, int n) {
+    size_t t = 0;
+    for (int i = 0; i < n; ++i) t += ctxs[i]->sp[0].items.size() + ctxs[i]->sp[1].items.size();
+    return t;
+}
+
+mde_status mde_group_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *bytes) {
+    if (!ctxs || n < 1 || !bytes) return MDE_INVALID;
+    size_t max_items = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || !ctxs[i]->bound) return MDE_STATE;
+        size_t mi = 0;
+        carve(ctxs[i], ctxs[i]->W, nullptr, &mi);
+        max_items += mi;
+    }
+    Carver cv{nullptr};
+    cv.take<InstDev>(n);
+    cv.take<MoveArgs>(n);
+    cv.take<WorkItem>(max_items);
+    *bytes = cv.off + 256;
+    return MDE_OK;
+}
+
+static mde_status group_rebuild(mde_group *g) {
+    const int n = (int)g->ctx.size();
+    std::vector<WorkItem> all;
+    std::vector<double> cost;
+    g->lds = 0;
+    g->maxW = 0;
+    g->nmax = 0;
+    g->mmax = 0;
+    for (int i = 0; i < n; ++i) {
+        mde_ctx *c = g->ctx[i];
+        g->maxW = std::max(g->maxW, c->W);
+        g->nmax = std::max(g->nmax, c->h.nmax);
+        g->mmax = std::max(g->mmax, c->h.mmax);
+        for (int s = 0; s < 2; ++s) {
+            g->ex_cap = std::max(g->ex_cap, c->sp[s].ex_cap);
+            for (WorkItem it : c->sp[s].items) {
+                it.inst = i;
+                all.push_back(it);
+                cost.push_back(order_cost(it.order) * (it.u1 - it.u0) * c->WT);
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int s = 0; s < 2; ++s) {
+            mde_ctx *c = g->ctx[i];
+            g->lds = std::max(g->lds, det_lds(c->sp[s], c->WT, g->threads, c->d.precision, true,
+                                              g->ex_cap));
+        }
+    std::vector<int> idx(all.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<WorkItem> sorted;
+    sorted.reserve(all.size());
+    for (int i : idx) sorted.push_back(all[i]);
+    g->n_items = (int)sorted.size();
+    if (!sorted.empty())
+        if (hipMemcpy(g->d_items, sorted.data(), sizeof(WorkItem) * sorted.size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            MDE_GFAIL(g, MDE_DEVICE, "upload of group items failed");
+    std::vector<InstDev> insts(n);
+    for (int i = 0; i < n; ++i) insts[i] = g->ctx[i]->h;
+    if (hipMemcpy(g->d_insts, insts.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice) != hipSuccess)
+        MDE_GFAIL(g, MDE_DEVICE, "upload of group descriptors failed");
+    const size_t lds = std::max<size_t>(g->lds, 1024);
+    int per_cu = (int)std::min<size_t>(160 * 1024 / lds, 2048 / g->threads);
+    per_cu = std::max(per_cu, 1);
+    g->grid = std::max(1, (int)std::min<size_t>(sorted.size(), (size_t)g->ctx[0]->n_cu * per_cu));
+    return MDE_OK;
+}
+
+mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t bytes,
+                            mde_group **out) {
+    if (!ctxs || n < 1 || !out || !dev) return MDE_INVALID;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || !ctxs[i]->bound) return MDE_STATE;
+        if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->d.precision != ctxs[0]->d.precision)
+            return MDE_INVALID;
+    }
+    size_t need = 0;
+    if (mde_group_workspace_bytes(ctxs, n, &need) != MDE_OK || bytes < need) return MDE_NOMEM;
+    mde_group *g = new (std::nothrow) mde_group();
+    if (!g) return MDE_NOMEM;
+    g->ctx.assign(ctxs, ctxs + n);
+    g->stream = ctxs[0]->stream;
+    g->prec = ctxs[0]->d.precision;
+    // one walker tile and block size for every instance of the launch
+    int WT = 64, thr = 64;
+    for (int i = 0; i < n; ++i) {
+        WT = std::min(WT, ctxs[i]->WT);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int s = 0; s < 2; ++s) thr = std::max(thr, ctxs[i]->sp[s].threads);
+    thr = std::max(thr, WT);
+    g->WT = WT;
+    g->threads = thr;
+    for (int i = 0; i < n; ++i) {
+        mde_ctx *c = ctxs[i];
+        c->WT = WT;
+        for (int s = 0; s < 2; ++s) c->sp[s].threads = thr;
+        mde_status st = apply_plan(c);
+        if (st) {
+            delete g;
+            return st;
+        }
+        (void)launch_init_misc(c->stream, c->d_inst, c->h);
+        c->initialized = false;
+    }
+    Carver cv{(char *)dev};
+    g->d_insts = cv.take<InstDev>(n);
+    g->d_moves = cv.take<MoveArgs>(n);
+    g->d_items = cv.take<WorkItem>(need / sizeof(WorkItem));
+    if (hipHostMalloc((void **)&g->pinned, sizeof(MoveArgs) * n * mde_group::RING) != hipSuccess) {
+        delete g;
+        return MDE_NOMEM;
+    }
+    for (int r = 0; r < mde_group::RING; ++r)
+        if (hipEventCreateWithFlags(&g->ev[r], hipEventDisableTiming) != hipSuccess) {
+            delete g;
+            return MDE_DEVICE;
+        }
+    g->hmoves.assign(n, MoveArgs{});
+    mde_status st = group_rebuild(g);
+    if (st) {
+        delete g;
+        return st;
+    }
+    *out = g;
+    return MDE_OK;
+}
+
+mde_status mde_group_destroy(mde_group *g) {
+    if (!g) return MDE_OK;
+    for (int r = 0; r < mde_group::RING; ++r)
+        if (g->ev[r]) (void)hipEventDestroy(g->ev[r]);
+    if (g->pinned) (void)hipHostFree(g->pinned);
+    for (void *p : g->capture_bufs) (void)hipHostFree(p);
+    delete g;
+    return MDE_OK;
+}
+
+// copy the per-instance move arguments to the device (stream-ordered)
+static mde_status group_upload(mde_group *g) {
+    const int n = (int)g->ctx.size();
+    MoveArgs *src = nullptr;
+    if (g->capturing) {
+        // a captured copy reads its host buffer at every replay: keep one per call
+        if (hipHostMalloc((void **)&src, sizeof(MoveArgs) * n) != hipSuccess)
+            MDE_GFAIL(g, MDE_NOMEM, "pinned buffer for capture");
+        g->capture_bufs.push_back(src);
+    } else {
+        const int r = g->ring_pos;
+        g->ring_pos = (g->ring_pos + 1) % mde_group::RING;
+        if (g->ev_used[r] && hipEventSynchronize(g->ev[r]) != hipSuccess)
+            MDE_GFAIL(g, MDE_DEVICE, "event wait");
+        src = g->pinned + (size_t)r * n;
+        std::memcpy(src, g->hmoves.data(), sizeof(MoveArgs) * n);
+        if (hipMemcpyAsync(g->d_moves, src, sizeof(MoveArgs) * n, hipMemcpyHostToDevice, g->stream) !=
+            hipSuccess)
+            MDE_GFAIL(g, MDE_DEVICE, "argument upload");
+        if (hipEventRecord(g->ev[r], g->stream) != hipSuccess) MDE_GFAIL(g, MDE_DEVICE, "event record");
+        g->ev_used[r] = true;
+        return MDE_OK;
+    }
+    std::memcpy(src, g->hmoves.data(), sizeof(MoveArgs) * n);
+    if (hipMemcpyAsync(g->d_moves, src, sizeof(MoveArgs) * n, hipMemcpyHostToDevice, g->stream) !=
+        hipSuccess)
+        MDE_GFAIL(g, MDE_DEVICE, "argument upload");
+    return MDE_OK;
+}
+
+mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const *new_orb,
+                             double *const *ratio, double *const *grad, double *const *lap,
+                             int32_t *const *status) {
+    if (!g || !e || !new_orb) return MDE_INVALID;
+    const int n = (int)g->ctx.size();
+    for (int i = 0; i < n; ++i) {
+        mde_ctx *c = g->ctx[i];
+        if (!c->initialized || c->adjoint_state) MDE_GFAIL(g, MDE_STATE, "instance %d not initialised", i);
+        if (e[i] < 0 || e[i] >= c->d.n_elec[0] + c->d.n_elec[1])
+            MDE_GFAIL(g, MDE_INVALID, "instance %d: electron out of range", i);
+        int row;
+        const int s = spin_of(c, e[i], &row);
+        mde_status st = ensure_C(c, s);
+        if (st) MDE_GFAIL(g, st, "instance %d: %s", i, c->err.c_str());
+        MoveArgs &m = g->hmoves[i];
+        m = MoveArgs{};
+        m.e = e[i];
+        m.spin = s;
+        m.row = row;
+        m.new_orb = new_orb[i];
+        m.ratio = ratio ? ratio[i] : nullptr;
+        m.grad = grad ? grad[i] : nullptr;
+        m.lap = lap ? lap[i] : nullptr;
+        m.status = status ? status[i] : nullptr;
+    }
+    mde_status st = group_upload(g);
+    if (st) return st;
+    const MoveArgs none = no_move();
+    if (launch_propose(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, g->prec, g->nmax,
+                       g->mmax, g->WT, (g->maxW + g->WT - 1) / g->WT) != hipSuccess)
+        MDE_GFAIL(g, MDE_DEVICE, "propose launch");
+    if (launch_det(g->stream, g->d_insts, n, g->d_items, g->n_items, g->ex_cap, g->d_moves, none,
+                   DM_PROPOSE, g->prec, g->WT, g->lds, g->threads, g->grid, g->ctx[0]->h.counter,
+                   nullptr, nullptr) != hipSuccess)
+        MDE_GFAIL(g, MDE_DEVICE, "determinant launch");
+    if (launch_finish(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, nullptr) != hipSuccess)
+        MDE_GFAIL(g, MDE_DEVICE, "finish launch");
+    for (int i = 0; i < n; ++i) g->ctx[i]->pending_e = e[i];
+    return MDE_OK;
+}
+
+mde_status mde_group_accept(mde_group *g, const int32_t *e, const uint8_t *const *accept) {
+    if (!g || !e || !accept) return MDE_INVALID;
+    const int n = (int)g->ctx.size();
+    for (int i = 0; i < n; ++i) {
+        mde_ctx *c = g->ctx[i];
+        if (c->pending_e != e[i]) MDE_GFAIL(g, MDE_STATE, "instance %d: no pending proposal", i);
+        int row;
+        const int s = spin_of(c, e[i], &row);
+        MoveArgs &m = g->hmoves[i];
+        m = MoveArgs{};
+        m.e = e[i];
+        m.spin = s;
+        m.row = row;
+        m.accept = accept[i];
+    }
+    mde_status st = group_upload(g);
+    if (st) return st;
+    const MoveArgs none = no_move();
+    if (launch_accept(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, g->prec, g->nmax,
+                      g->mmax, g->WT, (g->maxW + g->WT - 1) / g->WT) != hipSuccess)
+        MDE_GFAIL(g, MDE_DEVICE, "accept launch");
+    for (int i = 0; i < n; ++i) {
+        mde_ctx *c = g->ctx[i];
+        int row;
+        const int s = spin_of(c, e[i], &row);
+        c->R_valid[s] = false;
+        c->C_valid[1 - s] = false;
+        c->pending_e = -1;
+        c->accept_count++;
+        if (c->d.refresh_every > 0 && c->accept_count % c->d.refresh_every == 0) {
+            mde_status r = full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr);
+            if (r) MDE_GFAIL(g, r, "instance %d refresh: %s", i, c->err.c_str());
+        }
+    }
+    return MDE_OK;
+}
+
+mde_status mde_group_capture_begin(mde_group *g) {
+    if (!g) return MDE_INVALID;
+    if (g->capturing) MDE_GFAIL(g, MDE_STATE, "already capturing");
+    if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        MDE_GFAIL(g, MDE_DEVICE, "begin capture");
+    g->capturing = true;
+    for (mde_ctx *c : g->ctx) c->capturing = true;
+    return MDE_OK;
+}
+
+mde_status mde_group_capture_end(mde_group *g, mde_graph **out) {
+    if (!g || !out) return MDE_INVALID;
+    if (!g->capturing) MDE_GFAIL(g, MDE_STATE, "not capturing");
+    g->capturing = false;
+    for (mde_ctx *c : g->ctx) c->capturing = false;
+    mde_graph *gr = new (std::nothrow) mde_graph();
+    if (!gr) return MDE_NOMEM;
+    if (hipStreamEndCapture(g->stream, &gr->graph) != hipSuccess) {
+        delete gr;
+        MDE_GFAIL(g, MDE_DEVICE, "end capture");
+    }
+    if (hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        MDE_GFAIL(g, MDE_DEVICE, "instantiate");
+    }
+    gr->host_bufs.swap(g->capture_bufs);
+    *out = gr;
+    return MDE_OK;
+}
+
+const char *mde_group_error_string(const mde_group *g) { return g ? g->err.c_str() : "no group"; }
+
+}  // extern "C"

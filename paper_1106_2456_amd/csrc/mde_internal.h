@@ -1,0 +1,142 @@
+// Internal device-side data structures and kernel launchers of libmde.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mde {
+
+constexpr int MAXN = 64;     // electrons per spin
+constexpr int MAXM = 256;    // virtual orbitals per spin
+constexpr int MAXK = 8;      // excitation order
+constexpr int NSUM = 5;      // N, and the x, y, z, laplacian numerators
+
+// One unit of determinant work: excitations [u0, u1) of order `order` of
+// spin `spin` for the walkers of tile `tile` of instance `inst`.  Results go
+// to partial-sum slot `slot` of that instance and spin.
+struct WorkItem {
+    int32_t inst, spin, tile, order;
+    int32_t u0, u1, slot, pad;
+};
+
+// Per-spin device view of one instance.  Internal excitation order: sorted
+// by order, then holes, then particles; index 0 is the reference.
+struct SpinDev {
+    int32_t n, m, no, U;          // electrons, virtuals, orbitals, excitations
+    int32_t WT, WTP, n_tiles, n_slots;   // walker tile, LDS row stride
+    int32_t order_start[MAXK + 2];       // first u of each order (k = 0..9)
+    int32_t max_order;
+    int32_t pad0;
+    const uint4 *ex;          // [U] packed: bytes 0..7 holes, 8..15 particles - n
+    const int32_t *ci_seg;    // [U+1] CI terms of this spin's excitation u
+    const int32_t *ci_other;  // [n_det] other spin's excitation, per term
+    const int32_t *ci_idx;    // [n_det] original determinant index, per term
+    const int32_t *inv_off;   // [n*m+1] adjoint inverted index by entry
+    const int32_t *inv_ent;   // packed (u << 6) | (j << 3) | l
+    const int32_t *tile_slot; // [n_tiles+1] slots of each tile
+    const WorkItem *items;    // [n_slots] work items of this spin
+    double *Phi;     // [W][n][no] orbital values (current positions)
+    double *B;       // [W][n][n] inverse of the reference matrix
+    // Walker-tiled layout "[tile][e][WT]": element e of walker w sits at
+    // ((w / WT) * E + e) * WT + w % WT, E the row length (here n*m).
+    double *T;       // tiled [n*m] table, virtual block (FP64 mode)
+    float *T32;      // tiled [n*m] table (mixed mode)
+    float *PhiV32;   // [W][n][m] virtual orbital values in FP32 (mixed)
+    double *logdet;  // [W] log|det A0|
+    double *sgn;     // [W] sign det A0
+    double *R;       // [n_tiles][U][WT] excited ratios at current positions
+    double *C;       // [n_tiles][U][WT] CI weights: sum over terms of c_I R_other
+    double *partial; // [n_slots][WT][NSUM]
+    double *coef_s;  // [n_det] c_I in this spin's CI-term order
+    const int32_t *chunks;   // [2*n_chunks] (first, end) excitation ranges of the precontraction
+    const int4 *pieces;      // [n_pieces] (u, k0, k1, -) pieces of long CI segments
+    const int4 *longs;       // [n_longs] (u, first piece, end piece, -)
+    double *pc_part;         // [n_pieces][n_tiles][WT] partial sums of the pieces
+    int32_t n_chunks, n_pieces, n_longs, pad1;
+};
+
+struct InstDev {
+    SpinDev s[2];
+    int32_t W, prec, nmax, mmax, nomax, pad;
+    int64_t n_det;
+    const double *coef;   // [n_det] device copy
+    double *Nold;    // [W] current multi-determinant sum N = Psi/(D0up D0dn)
+    double *Nnew;    // [W] proposed N'
+    double *rho;     // [W] det A'/det A
+    // proposal of the moving spin (n, m of that spin), walker-tiled:
+    double *cp;      // tiled [n]    c' = A'^-1 e_i
+    double *Tp;      // tiled [n*m]  T'_V (FP64 mode)
+    double *g;       // tiled [4*m]  g^a (FP64 mode)
+    double *rhoA;    // [W][4] rho^a
+    double *newrow;  // [W][nomax] proposed orbital values of the moved electron
+    float *g32;      // tiled [4*m] (mixed)
+    float *cp32;     // tiled [n] (mixed)
+    float *Tp32;     // tiled [n*m] proposed table (mixed)
+    float *Ap32;     // [W][nmax+4][nmax] rows of A'^-1 then e^a (mixed GEMM operand)
+    int32_t *st;     // [W] internal status bits
+    int32_t *counter;  // work-queue counter of the persistent kernel
+    double *Lnew;    // [W] scratch
+};
+
+// Per-call move arguments (device array for groups, by value otherwise).
+struct MoveArgs {
+    int32_t e, spin, row, mode;   // electron, its spin, its row in A
+    const double *new_orb;        // [W][5][no]
+    double *ratio, *grad, *lap;
+    int32_t *status;
+    const uint8_t *accept;
+};
+
+enum DetMode { DM_PROPOSE = 0, DM_VALUES = 1 };
+
+// Pointers read from descriptors are generic to the compiler; these casts
+// make their loads global-memory loads (no LDS counter involvement).
+#define MDE_G(T, p) ((const T __attribute__((address_space(1))) *)(p))
+#define MDE_GW(T, p) ((T __attribute__((address_space(1))) *)(p))
+
+// Largest excitation range of one work item (its records are staged in LDS).
+constexpr int ITEM_MAX = 1024;
+
+// ---- launchers (stream-ordered) -------------------------------------------
+// All launchers take the device array `insts` and either a single instance
+// index range or work-item lists.
+
+hipError_t launch_lu_inverse(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                             int spin, const double *orb_in, int32_t *status);
+hipError_t launch_table_gemm(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                             int spin);
+hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
+                          const MoveArgs *d_moves, const MoveArgs &m1, int prec,
+                          int nmax, int mmax, int WT, int max_tiles);
+hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst,
+                      const WorkItem *items, int n_items, int ex_cap,
+                      const MoveArgs *d_moves, const MoveArgs &m1, int mode, int prec,
+                      int WT, size_t lds_bytes, int threads, int grid, int32_t *counter,
+                      const double *tab0, const double *tab1);
+hipError_t launch_finish(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
+                         const MoveArgs *d_moves, const MoveArgs &m1, int32_t *counter);
+hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
+                         const MoveArgs *d_moves, const MoveArgs &m1, int prec,
+                         int nmax, int mmax, int WT, int max_tiles);
+hipError_t launch_precontract(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                              int spin, const double *coef);
+hipError_t launch_coef_gather(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                              const double *coef);
+hipError_t launch_nsum(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                       double *log_abs_psi, double *sign_psi, int32_t *status, int with_ref);
+hipError_t launch_init_misc(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst);
+hipError_t launch_export(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                         int what, int spin, double *dst, const int32_t *perm_user);
+hipError_t launch_backward(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                           const double *go, const double *Nw, const double *coef,
+                           double *grad_coef, double *grad_T_up, double *grad_T_dn,
+                           const double *T_up, const double *T_dn);
+hipError_t launch_eval_finish(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                              double *log_abs, double *sign, int32_t *status);
+hipError_t launch_sgauss(hipStream_t st, int nb, const double *centres, const double *expo,
+                         int n_orb, const double *mo, int npos, const double *pos,
+                         double *out);
+hipError_t launch_reset_counter(hipStream_t st, int32_t *counter);
+hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int32_t v, size_t n);
+
+}  // namespace mde
