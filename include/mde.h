@@ -60,9 +60,15 @@ typedef enum {
 
 typedef enum {
     MDE_FP64 = 0,         /* every step in FP64 (the reference form)          */
-    MDE_MIXED = 1         /* table GEMM and small determinants in FP32 (MFMA
-                             for the GEMM); LU, Sherman-Morrison denominators,
-                             CI coefficients and CI sums stay FP64            */
+    MDE_MIXED = 1,        /* tables stored in FP32 (half the LDS and memory
+                             traffic of the determinant stage); the
+                             Sherman-Morrison table update, the small
+                             determinants, LU, denominators and CI sums are
+                             computed in FP64                                 */
+    MDE_MIXED_GEMM = 2    /* as MDE_MIXED, but every proposal rebuilds the
+                             table with one FP32 MFMA GEMM T' = A'^-1 Phi'_V
+                             (Algorithm 1 step 3); its error grows with the
+                             condition number of the reference matrix         */
 } mde_precision;
 
 /* per-walker status bits */
@@ -218,12 +224,12 @@ mde_status mde_graph_destroy(mde_graph *g);
 
 /* ---- uneven batch ------------------------------------------------------- */
 
-/* Pack n bound contexts (same stream, same precision) so that one propose
- * runs as one persistent launch of the determinant kernel over the work
- * items of every instance (Sec. V: the tiny determinants are independent).
- * All contexts are switched to one common walker tile; call mde_init (or
- * mde_refresh) on each context after mde_group_create.  The group's tables
- * live in caller-owned device memory of mde_group_workspace_bytes bytes. */
+/* Pack n bound contexts (same stream, same precision, same walker tile --
+ * set it with mde_set_plan before binding) so that one propose runs as one
+ * persistent launch of the determinant kernel over the work items of every
+ * instance (Sec. V: the tiny determinants are independent).  The group's
+ * tables live in caller-owned device memory of mde_group_workspace_bytes
+ * bytes.  MDE_INVALID if the walker tiles differ. */
 mde_status mde_group_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *bytes);
 mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t bytes,
                             mde_group **out);

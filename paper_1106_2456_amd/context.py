@@ -13,7 +13,9 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from ._lib import (MDE_FP64, MDE_MIXED, MdeDesc, MdeError, lib)
+from ._lib import (MDE_FP64, MDE_MIXED, MDE_MIXED_GEMM, MdeDesc, MdeError, lib)
+
+PRECISIONS = {"fp64": MDE_FP64, "mixed": MDE_MIXED, "mixed_gemm": MDE_MIXED_GEMM}
 
 
 def _ptr(t) -> Optional[int]:
@@ -80,7 +82,9 @@ class Context:
         d.max_walkers = self.max_walkers
         d.max_order = int(max_order)
         d.refresh_every = int(refresh_every)
-        d.precision = MDE_FP64 if precision == "fp64" else MDE_MIXED
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        d.precision = PRECISIONS[precision]
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
@@ -275,9 +279,25 @@ class Context:
 
 
 class Group:
-    """Uneven batch: several bound contexts packed into one persistent launch."""
+    """Uneven batch: several contexts packed into one persistent launch.
 
-    def __init__(self, ctxs: Sequence[Context]):
+    Pass contexts whose expansion is set but which are not bound yet, with
+    their walker counts: the group gives them one common walker tile (the
+    smallest of their defaults) and binds them.  Already-bound contexts must
+    share a walker tile."""
+
+    @staticmethod
+    def prepare(ctxs: Sequence[Context], Ws: Sequence[int]):
+        wt = min(min(c.get_plan(0)["walker_tile"], c.get_plan(1)["walker_tile"]) for c in ctxs)
+        for c, W in zip(ctxs, Ws):
+            for sp in (0, 1):
+                c.set_plan(sp, walker_tile=wt)
+            c.bind(W)
+        return wt
+
+    def __init__(self, ctxs: Sequence[Context], Ws: Optional[Sequence[int]] = None):
+        if Ws is not None:
+            Group.prepare(ctxs, Ws)
         self.ctxs = list(ctxs)
         arr = (C.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
         self._arr = arr

@@ -26,7 +26,11 @@ __device__ __forceinline__ int exc_byte(const uint4 &x, int i) {
 // One order-K excitation for walker-lane wl.  PROPOSE: accumulate
 // C_u * (R_u, G^x_u, G^y_u, G^z_u, G^L_u) with
 //   R_u = det S,  G^a_u = rho^a R_u + sum_j g^a[p_j] y_j,  y = adj(S) c'[h].
-// VALUES: return det S.
+// VALUES: return det S.  Table entries are stored as TT (FP64, or FP32 in
+// the mixed form); the small-determinant arithmetic is always FP64 (in the
+// mixed form FP32 arithmetic lost up to 1e-3 on triples and quadruples
+// through cancellation, FP64 arithmetic on the FP32 entries keeps the
+// table's own accuracy).
 template <int K, typename TT, int MODE>
 __device__ __forceinline__ double det_one(const uint4 &ex, const TT *__restrict__ tabs,
                                           const TT *__restrict__ gs, const TT *__restrict__ cs,
@@ -39,28 +43,27 @@ __device__ __forceinline__ double det_one(const uint4 &ex, const TT *__restrict_
         hm[j] = h[j] * m;
         p[j] = exc_byte(ex, 8 + j);
     }
-    TT col[K][K];
+    double col[K][K];
 #pragma unroll
     for (int j = 0; j < K; ++j)
 #pragma unroll
-        for (int r = 0; r < K; ++r) col[j][r] = tabs[(hm[r] + p[j]) * WTP + wl];
-    TT c[K], y[K];
+        for (int r = 0; r < K; ++r) col[j][r] = (double)tabs[(hm[r] + p[j]) * WTP + wl];
+    double c[K], y[K];
     if (MODE == DM_VALUES) {
 #pragma unroll
-        for (int r = 0; r < K; ++r) c[r] = TT(0);
-        return (double)SmallDet<K, TT>::run(col, c, y);
+        for (int r = 0; r < K; ++r) c[r] = 0.0;
+        return SmallDet<K, double>::run(col, c, y);
     }
 #pragma unroll
-    for (int r = 0; r < K; ++r) c[r] = cs[h[r] * WTP + wl];
-    const TT det = SmallDet<K, TT>::run(col, c, y);
-    const double dd = (double)det;
+    for (int r = 0; r < K; ++r) c[r] = (double)cs[h[r] * WTP + wl];
+    const double dd = SmallDet<K, double>::run(col, c, y);
     acc[0] = fma(Cu, dd, acc[0]);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        TT s = TT(0);
+        double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < K; ++j) s = fma(gs[(a * m + p[j]) * WTP + wl], y[j], s);
-        const double G = fma(rhoA[a], dd, (double)s);
+        for (int j = 0; j < K; ++j) s = fma((double)gs[(a * m + p[j]) * WTP + wl], y[j], s);
+        const double G = fma(rhoA[a], dd, s);
         acc[1 + a] = fma(Cu, G, acc[1 + a]);
     }
     return dd;
@@ -76,18 +79,17 @@ __device__ double det_one_generic(int k, const uint4 &ex, const TT *__restrict__
         h[j] = exc_byte(ex, j);
         p[j] = exc_byte(ex, 8 + j);
     }
-    TT col[8][8], c[8], y[8];
+    double col[8][8], c[8], y[8];
     for (int j = 0; j < k; ++j)
-        for (int r = 0; r < k; ++r) col[j][r] = tabs[(h[r] * m + p[j]) * WTP + wl];
-    for (int r = 0; r < k; ++r) c[r] = (MODE == DM_VALUES) ? TT(0) : cs[h[r] * WTP + wl];
-    const TT det = small_det_generic<TT>(k, col, c, y);
-    const double dd = (double)det;
+        for (int r = 0; r < k; ++r) col[j][r] = (double)tabs[(h[r] * m + p[j]) * WTP + wl];
+    for (int r = 0; r < k; ++r) c[r] = (MODE == DM_VALUES) ? 0.0 : (double)cs[h[r] * WTP + wl];
+    const double dd = small_det_generic<double>(k, col, c, y);
     if (MODE == DM_VALUES) return dd;
     acc[0] = fma(Cu, dd, acc[0]);
     for (int a = 0; a < 4; ++a) {
-        TT s = TT(0);
-        for (int j = 0; j < k; ++j) s = fma(gs[(a * m + p[j]) * WTP + wl], y[j], s);
-        const double G = fma(rhoA[a], dd, (double)s);
+        double s = 0.0;
+        for (int j = 0; j < k; ++j) s = fma((double)gs[(a * m + p[j]) * WTP + wl], y[j], s);
+        const double G = fma(rhoA[a], dd, s);
         acc[1 + a] = fma(Cu, G, acc[1 + a]);
     }
     return dd;

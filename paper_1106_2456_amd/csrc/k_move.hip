@@ -36,10 +36,10 @@ k_lu_inverse(const InstDev *__restrict__ insts, int spin, const double *__restri
             const int i = idx / no, p = idx - i * no;
             const double v = orb_in[((size_t)(w * n + i) * 5) * no + p];
             S.Phi[(size_t)w * n * no + idx] = v;
-            if (I.prec == 1 && p >= n)
+            if (I.prec == 2 && p >= n)
                 S.PhiV32[((size_t)w * n + i) * S.m + (p - n)] = (float)v;
         }
-    } else if (I.prec == 1) {
+    } else if (I.prec == 2) {
         for (int idx = lane; idx < n * S.m; idx += 64) {
             const int i = idx / S.m, p = idx - i * S.m;
             S.PhiV32[(size_t)w * n * S.m + idx] = (float)S.Phi[((size_t)w * n + i) * no + n + p];
@@ -192,7 +192,9 @@ hipError_t launch_table_gemm(hipStream_t st, const InstDev *d_inst, const InstDe
 // kernel stages into LDS.
 // ---------------------------------------------------------------------------
 
-template <int WT>
+// TT = double: FP64 tables.  TT = float (MIXED): FP32 table storage, every
+// product and the rank-one update in FP64, results rounded once to FP32.
+template <int WT, typename TT>
 __global__ void __launch_bounds__(1024)
 k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1) {
     const int inst = blockIdx.y;
@@ -253,16 +255,24 @@ k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ move
         }
     }
     __syncthreads();
-    const auto Tt = MDE_G(double, S.T) + (size_t)t * nm * WT;
-    const auto Tpt = MDE_GW(double, I.Tp) + (size_t)t * nm * WT;
-    const auto gt = MDE_GW(double, I.g) + (size_t)t * 4 * m * WT;
-    const auto cpt = MDE_GW(double, I.cp) + (size_t)t * n * WT;
-    for (int idx = tid; idx < n * WT; idx += nthr) cpt[idx] = c_s[idx] * ir_s[idx % WT];
+    const bool f64 = sizeof(TT) == 8;
+    const auto Tt = MDE_G(TT, f64 ? (const void *)S.T : (const void *)S.T32) + (size_t)t * nm * WT;
+    const auto Tpt = MDE_GW(TT, f64 ? (void *)I.Tp : (void *)I.Tp32) + (size_t)t * nm * WT;
+    const auto gt = MDE_GW(TT, f64 ? (void *)I.g : (void *)I.g32) + (size_t)t * 4 * m * WT;
+    // c' in FP64 for the commit's update of A^-1, and in the table type for
+    // the determinant kernel
+    const auto cpd = MDE_GW(double, I.cp) + (size_t)t * n * WT;
+    const auto cpt = MDE_GW(TT, f64 ? (void *)I.cp : (void *)I.cp32) + (size_t)t * n * WT;
+    for (int idx = tid; idx < n * WT; idx += nthr) {
+        const double v = c_s[idx] * ir_s[idx % WT];
+        cpd[idx] = v;
+        if (!f64) cpt[idx] = (TT)v;
+    }
     for (int idx = tid; idx < m * WT; idx += nthr) {
         const int p = idx / WT, l = idx % WT, w = t * WT + l;
         double v = 0.0, wa[4] = {0, 0, 0, 0};
         for (int r = 0; r < n; ++r) {
-            const double tv = Tt[(size_t)(r * m + p) * WT + l];
+            const double tv = (double)Tt[(size_t)(r * m + p) * WT + l];
             v = fma(a_s[r * WT + l], tv, v);
 #pragma unroll
             for (int a = 0; a < 4; ++a) wa[a] = fma(d_s[(a * n + r) * WT + l], tv, wa[a]);
@@ -277,11 +287,11 @@ k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ move
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-            gt[(size_t)(a * m + p) * WT + l] = (w < W) ? dv[a] - wa[a] + rA_s[a * WT + l] * q : 0.0;
+            gt[(size_t)(a * m + p) * WT + l] = (TT)((w < W) ? dv[a] - wa[a] + rA_s[a * WT + l] * q : 0.0);
         const double qi = q * ir_s[l];
         for (int r = 0; r < n; ++r) {
             const size_t o = (size_t)(r * m + p) * WT + l;
-            Tpt[o] = fma(-c_s[r * WT + l], qi, Tt[o]);
+            Tpt[o] = (TT)fma(-c_s[r * WT + l], qi, (double)Tt[o]);
         }
     }
     for (int idx = tid; idx < no * WT; idx += nthr) {
@@ -404,20 +414,26 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
     float *__restrict__ g32 = I.g32 + (size_t)tw * 4 * m * WT + lw;
     for (int t = wave; t < RT * CT; t += 4) {
         const int rt = t / CT, ct = t - rt * CT;
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        // each MFMA multiplies FP32 operands over a K-block of 4 with FP32
+        // accumulation; the K-blocks are summed in FP64 (FP32 accumulation
+        // over all of K = n left the worst-conditioned walkers above 1e-5)
+        double acc64[4] = {0.0, 0.0, 0.0, 0.0};
         for (int kk = 0; kk < kp; kk += 4) {
             const float a = As[(rt * 16 + lr) * lda + kk + lk];
             const float b = Bs[(kk + lk) * mp + ct * 16 + lr];
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            const floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+            const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, z, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc64[i] += (double)acc[i];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = rt * 16 + 4 * lk + i, p = ct * 16 + lr;
             if (p >= m) continue;
-            if (r < n) Tp[(size_t)(r * m + p) * WT] = acc[i];
+            if (r < n) Tp[(size_t)(r * m + p) * WT] = (float)acc64[i];
             else if (r < rows) {
                 const int a = r - n;
-                g32[(size_t)(a * m + p) * WT] = (float)nr[(1 + a) * no + n + p] - acc[i];
+                g32[(size_t)(a * m + p) * WT] = (float)(nr[(1 + a) * no + n + p] - acc64[i]);
             }
         }
     }
@@ -426,16 +442,19 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
 hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                           const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
                           int mmax, int WT, int max_tiles) {
-    if (prec == 0) {
+    if (prec == 0 || prec == 1) {
         const int threads = WT >= 16 ? 1024 : 256;
         const size_t lds = sizeof(double) * ((size_t)6 * nmax * WT + 5 * WT);
         dim3 g(max_tiles, n_inst);
-#define MDE_PP(X)                                                                             \
-    case X:                                                                                   \
-        if (lds > 65536)                                                                      \
-            (void)hipFuncSetAttribute((const void *)k_propose64<X>,                           \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
-        hipLaunchKernelGGL(k_propose64<X>, g, dim3(threads), lds, st, d_insts, d_moves, m1); \
+#define MDE_PP(X)                                                                                \
+    case X:                                                                                      \
+        if (prec == 0) {                                                                         \
+            hipLaunchKernelGGL((k_propose64<X, double>), g, dim3(threads), lds, st, d_insts,    \
+                               d_moves, m1);                                                     \
+        } else {                                                                                 \
+            hipLaunchKernelGGL((k_propose64<X, float>), g, dim3(threads), lds, st, d_insts,     \
+                               d_moves, m1);                                                     \
+        }                                                                                        \
         break;
         switch (WT) {
             MDE_PP(1) MDE_PP(2) MDE_PP(4) MDE_PP(8) MDE_PP(16) MDE_PP(32) MDE_PP(64)
@@ -511,9 +530,12 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
     } else {
         for (int idx = tid; idx < nm * WT; idx += nthr)
             if (acc_s[idx % WT]) S.T32[tb + idx] = I.Tp32[tb + idx];
-        for (int idx = tid; idx < m * WT; idx += nthr) {
-            const int p = idx / WT, l = idx % WT, w = t * WT + l;
-            if (acc_s[l]) S.PhiV32[((size_t)w * n + row) * m + p] = (float)nrow[(size_t)w * I.nomax + n + p];
+        if (I.prec == 2) {
+            for (int idx = tid; idx < m * WT; idx += nthr) {
+                const int p = idx / WT, l = idx % WT, w = t * WT + l;
+                if (acc_s[l])
+                    S.PhiV32[((size_t)w * n + row) * m + p] = (float)nrow[(size_t)w * I.nomax + n + p];
+            }
         }
     }
     for (int idx = tid; idx < no * WT; idx += nthr) {

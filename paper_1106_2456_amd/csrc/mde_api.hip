@@ -102,7 +102,12 @@ struct mde_ctx {
     long accept_count = 0;
     bool capturing = false;
     const double *last_T[2] = {nullptr, nullptr};   // tables of the last mde_eval_tables
+    // plan fields chosen by the caller (kept when the default plan is applied)
+    bool user_wt = false, user_thr[2] = {false, false}, user_item[2] = {false, false};
 };
+
+// default plan for W walkers, keeping the fields the caller set
+static void apply_default_plan(mde_ctx *c, int W);
 
 struct mde_group {
     std::vector<mde_ctx *> ctx;
@@ -278,6 +283,19 @@ static Plan default_plan(const mde_ctx *c, int W) {
     return p;
 }
 
+static void apply_default_plan(mde_ctx *c, int W) {
+    const Plan p = default_plan(c, W);
+    if (!c->user_wt) c->WT = p.WT;
+    for (int s = 0; s < 2; ++s) {
+        if (!c->user_thr[s]) c->sp[s].threads = (c->WT >= 16) ? 1024 : 256;
+        if (!c->user_item[s]) {
+            const size_t lds = det_lds(c->sp[s], c->WT, c->sp[s].threads, c->d.precision, true);
+            c->sp[s].item_exc = item_size_for(c, c->sp[s], W, c->WT, c->sp[s].threads, lds);
+        }
+        if (c->sp[s].threads < c->WT) c->sp[s].threads = std::max(64, c->WT);
+    }
+}
+
 static std::vector<Plan> candidate_plans(const mde_ctx *c, int W) {
     std::vector<Plan> out;
     Plan d = default_plan(c, W);
@@ -308,7 +326,9 @@ static std::vector<Plan> candidate_plans(const mde_ctx *c, int W) {
 // size the workspace for W walkers; assign pointers when base != nullptr
 static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullptr) {
     Carver cv{base};
-    InstDev &h = c->h;
+    // a sizing pass (base == nullptr) must leave the bound descriptor alone
+    InstDev scratch{};
+    InstDev &h = base ? c->h : scratch;
     const int prec = c->d.precision;
     const int nmax = std::max(c->sp[0].n, c->sp[1].n);
     const int mmax = std::max(c->sp[0].m, c->sp[1].m);
@@ -351,8 +371,8 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
         S.Phi = cv.take<double>((size_t)W * sp.n * sp.no);
         S.B = cv.take<double>((size_t)W * sp.n * sp.n);
         S.T = prec == 0 ? cv.take<double>(Wp * sp.n * sp.m) : nullptr;
-        S.T32 = prec == 1 ? cv.take<float>(Wp * sp.n * sp.m) : nullptr;
-        S.PhiV32 = prec == 1 ? cv.take<float>((size_t)W * sp.n * sp.m) : nullptr;
+        S.T32 = prec != 0 ? cv.take<float>(Wp * sp.n * sp.m) : nullptr;
+        S.PhiV32 = prec == 2 ? cv.take<float>((size_t)W * sp.n * sp.m) : nullptr;
         S.logdet = cv.take<double>(W);
         S.sgn = cv.take<double>(W);
         S.R = cv.take<double>(Wp * sp.U);
@@ -394,10 +414,10 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
     h.rhoA = cv.take<double>((size_t)W * 4);
     h.g = prec == 0 ? cv.take<double>(Wq * 4 * mmax) : nullptr;
     h.newrow = cv.take<double>((size_t)W * nomax);
-    h.g32 = prec == 1 ? cv.take<float>(Wq * 4 * mmax) : nullptr;
-    h.cp32 = prec == 1 ? cv.take<float>(Wq * nmax) : nullptr;
-    h.Tp32 = prec == 1 ? cv.take<float>(Wq * nmax * mmax) : nullptr;
-    h.Ap32 = prec == 1 ? cv.take<float>((size_t)W * (nmax + 4) * nmax) : nullptr;
+    h.g32 = prec != 0 ? cv.take<float>(Wq * 4 * mmax) : nullptr;
+    h.cp32 = prec != 0 ? cv.take<float>(Wq * nmax) : nullptr;
+    h.Tp32 = prec != 0 ? cv.take<float>(Wq * nmax * mmax) : nullptr;
+    h.Ap32 = prec == 2 ? cv.take<float>((size_t)W * (nmax + 4) * nmax) : nullptr;
     h.st = cv.take<int32_t>(W);
     h.counter = cv.take<int32_t>(64);
     h.Lnew = cv.take<double>(W);
@@ -540,7 +560,9 @@ mde_status mde_create(const mde_desc *desc, void *hip_stream, mde_ctx **out) {
     }
     if (desc->max_walkers < 1 || desc->max_order < 1 || desc->max_order > MDE_MAX_ORDER)
         return MDE_INVALID;
-    if (desc->precision != MDE_FP64 && desc->precision != MDE_MIXED) return MDE_INVALID;
+    if (desc->precision != MDE_FP64 && desc->precision != MDE_MIXED &&
+        desc->precision != MDE_MIXED_GEMM)
+        return MDE_INVALID;
     mde_ctx *c = new (std::nothrow) mde_ctx();
     if (!c) return MDE_NOMEM;
     c->d = *desc;
@@ -727,13 +749,7 @@ mde_status mde_set_ci(mde_ctx *c, int64_t n_det, const double *coef, const int32
         if (sp.chunks.empty()) { sp.chunks.push_back(0); sp.chunks.push_back(0); }
     }
     c->have_ci = true;
-    // default plan
-    Plan p = default_plan(c, c->d.max_walkers);
-    c->WT = p.WT;
-    for (int s = 0; s < 2; ++s) {
-        c->sp[s].threads = p.threads[s];
-        c->sp[s].item_exc = p.item_exc[s];
-    }
+    apply_default_plan(c, c->d.max_walkers);
     return MDE_OK;
 }
 
@@ -754,14 +770,7 @@ mde_status mde_workspace_bytes(const mde_ctx *cc, int32_t W, size_t *bytes) {
     if (!c || !bytes) return MDE_INVALID;
     if (!c->have_ci) MDE_FAIL(c, MDE_STATE, "set excitations and CI first");
     if (W < 1 || W > c->d.max_walkers) MDE_FAIL(c, MDE_INVALID, "W out of range");
-    Plan p = default_plan(c, W);
-    if (!c->bound) {
-        c->WT = p.WT;
-        for (int s = 0; s < 2; ++s) {
-            c->sp[s].threads = p.threads[s];
-            c->sp[s].item_exc = p.item_exc[s];
-        }
-    }
+    if (!c->bound) apply_default_plan(c, W);
     *bytes = carve(c, W, nullptr) + 256;
     return MDE_OK;
 }
@@ -773,12 +782,7 @@ mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
     if (W < 1 || W > c->d.max_walkers) MDE_FAIL(c, MDE_INVALID, "W out of range");
     if (((uintptr_t)dev) % 256) MDE_FAIL(c, MDE_INVALID, "workspace must be 256-byte aligned");
     size_t need = 0;
-    Plan p = default_plan(c, W);
-    c->WT = p.WT;
-    for (int s = 0; s < 2; ++s) {
-        c->sp[s].threads = p.threads[s];
-        c->sp[s].item_exc = p.item_exc[s];
-    }
+    apply_default_plan(c, W);
     need = carve(c, W, nullptr);
     if (bytes < need) MDE_FAIL(c, MDE_NOMEM, "workspace has %zu bytes, needs %zu", bytes, need);
     c->W = W;
@@ -979,14 +983,17 @@ mde_status mde_set_plan(mde_ctx *c, int32_t spin, int32_t walker_tile, int32_t i
         if (walker_tile < 1 || walker_tile > 64 || (walker_tile & (walker_tile - 1)))
             MDE_FAIL(c, MDE_INVALID, "walker tile must be a power of two in 1..64");
         c->WT = walker_tile;
+        c->user_wt = true;
     }
     if (threads) {
         if (threads < 64 || threads > 1024 || threads % 64) MDE_FAIL(c, MDE_INVALID, "bad thread count");
         c->sp[spin].threads = threads;
+        c->user_thr[spin] = true;
     }
     if (item_exc) {
         if (item_exc < 1) MDE_FAIL(c, MDE_INVALID, "bad item size");
         c->sp[spin].item_exc = item_exc;
+        c->user_item[spin] = true;
     }
     for (int s = 0; s < 2; ++s)
         if (c->sp[s].threads < c->WT) c->sp[s].threads = std::max(64, c->WT);
@@ -1261,28 +1268,18 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
     g->ctx.assign(ctxs, ctxs + n);
     g->stream = ctxs[0]->stream;
     g->prec = ctxs[0]->d.precision;
-    // one walker tile and block size for every instance of the launch
-    int WT = 64, thr = 64;
+    // every instance of the launch must share one walker tile (set it with
+    // mde_set_plan before binding); blocks use the largest thread count
+    int thr = 64;
     for (int i = 0; i < n; ++i) {
-        WT = std::min(WT, ctxs[i]->WT);
-    }
-    for (int i = 0; i < n; ++i)
-        for (int s = 0; s < 2; ++s) thr = std::max(thr, ctxs[i]->sp[s].threads);
-    thr = std::max(thr, WT);
-    g->WT = WT;
-    g->threads = thr;
-    for (int i = 0; i < n; ++i) {
-        mde_ctx *c = ctxs[i];
-        c->WT = WT;
-        for (int s = 0; s < 2; ++s) c->sp[s].threads = thr;
-        mde_status st = apply_plan(c);
-        if (st) {
+        if (ctxs[i]->WT != ctxs[0]->WT) {
             delete g;
-            return st;
+            return MDE_INVALID;
         }
-        (void)launch_init_misc(c->stream, c->d_inst, c->h);
-        c->initialized = false;
+        for (int s = 0; s < 2; ++s) thr = std::max(thr, ctxs[i]->sp[s].threads);
     }
+    g->WT = ctxs[0]->WT;
+    g->threads = std::max(thr, g->WT);
     Carver cv{(char *)dev};
     g->d_insts = cv.take<InstDev>(n);
     g->d_moves = cv.take<MoveArgs>(n);

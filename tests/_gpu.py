@@ -15,7 +15,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make_ctx(wl, precision="fp64", W=None, refresh_every=None, max_order=None):
+def make_ctx(wl, precision="fp64", W=None, refresh_every=None, max_order=None, bind=True):
     from paper_1106_2456_amd import Context
     s = wl.system
     W = W if W is not None else wl.walkers.W
@@ -25,7 +25,8 @@ def make_ctx(wl, precision="fp64", W=None, refresh_every=None, max_order=None):
     ctx.set_expansion(s.exc[0], s.exc[1], s.coef, s.det_up, s.det_dn)
     for sp in (0, 1):
         ctx.set_basis(sp, s.centres, s.expo, s.mo_spin(sp))
-    ctx.bind(W)
+    if bind:
+        ctx.bind(W)
     return ctx
 
 

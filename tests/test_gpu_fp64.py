@@ -108,3 +108,19 @@ def test_trajectory_batched_walkers_and_state():
             A = orb[w, :, 0, :n]
             assert np.abs(B[w] @ A - np.eye(n)).max() <= 1e-11 * np.linalg.cond(A)
             assert abs(ld[w] - np.linalg.slogdet(A)[1]) <= 1e-11 * np.linalg.cond(A)
+
+
+def test_sizing_query_after_bind_keeps_state():
+    """Regression: a workspace-size query on a bound context must not touch
+    its device descriptors (it once replaced them with null pointers)."""
+    wl = synth.water_like(1, W=4, n_det=120, n_moves=3)
+    ctx = make_ctx(wl)
+    assert ctx.workspace_bytes(4) > 0
+    pos = wl.walkers.pos.copy()
+    ou, od = gpu_orbitals(ctx, pos)
+    la, sg, st = ctx.init(ou, od)
+    e = int(wl.moves.electron[0])
+    new_r = pos[:, e] + wl.moves.disp[0]
+    ratio, grad, lap, st = ctx.propose(e, ctx.sgauss_eval(0, dev(new_r)))
+    ref = oracle.move(wl.system, pos, e, new_r)
+    assert scaled_err(ratio.cpu().numpy(), ref["ratio"], ref["scale_ratio"]).max() <= TOL
