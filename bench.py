@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the multi-determinant table method on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,mixed]
+
+Workload (headline): the water-like batched system -- 5 up + 5 down
+electrons, 5 occupied + 20 virtual orbitals per spin from 40 s-Gaussians on
+the three water nuclei, 10 000 determinants of orders 1-4, 4096 walkers, all
+inputs seeded and synthetic.  One step is one sweep: every electron proposes
+one move (ratio, gradient and laplacian of every determinant for every
+walker) and the seeded 50 % acceptance mask commits it; the state is
+recomputed from scratch once per sweep.  The K timed sweeps run as one HIP
+graph with all inputs resident in device memory.
+
+Metric: walker.det/s = walkers x determinants x moves / time.  The JSON line
+also carries the roofline of the determinant kernel (FP64 vector ALU), the
+CPU oracle timed on a bounded sample of the same workload, and the other
+precision forms.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X, 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
+PEAK_HBM_GBS = 8000.0
+
+# FP64 flops of one excitation of order k in the determinant kernel
+# (determinant, y = adj(S) c', four bordered derivative terms, five CI
+# accumulations); FMA counts 2.  See the design doc for the derivation.
+DET_FLOPS = {1: 26, 2: 43, 3: 80, 4: 165}
+
+
+def det_flops(k: int) -> int:
+    if k in DET_FLOPS:
+        return DET_FLOPS[k]
+    # generic path: k+1 eliminations of k x k (2k^3/3 each) + 4(2k+2) + 10
+    return int((k + 1) * 2 * k ** 3 / 3 + 4 * (2 * k + 2) + 10)
+
+
+def flops_per_launch(exc, W: int) -> float:
+    orders = exc.orders()
+    return float(W) * sum(det_flops(int(k)) for k in orders if k > 0)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_context(wl, precision, stream, refresh_every):
+    from paper_1106_2456_amd import Context
+    s = wl.system
+    W = wl.walkers.W
+    ctx = Context(s.n_elec, s.n_orb, W, max_order=4, refresh_every=refresh_every,
+                  precision=precision, stream=stream)
+    ctx.set_expansion(s.exc[0], s.exc[1], s.coef, s.det_up, s.det_dn)
+    for sp in (0, 1):
+        ctx.set_basis(sp, s.centres, s.expo, s.mo_spin(sp))
+    ctx.bind(W)
+    return ctx
+
+
+def run_form(wl, precision, steps, warmup, autotune=True):
+    """Time `steps` sweeps (one graph) of one precision form; returns a dict."""
+    import torch
+    s = wl.system
+    W = wl.walkers.W
+    n_tot = s.n_elec[0] + s.n_elec[1]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = build_context(wl, precision, stream, refresh_every=n_tot)
+        pos = torch.as_tensor(wl.walkers.pos, device="cuda")
+        nu = s.n_elec[0]
+        ou = ctx.sgauss_eval(0, pos[:, :nu].contiguous())
+        od = ctx.sgauss_eval(1, pos[:, nu:].contiguous())
+        ctx.init(ou, od)
+        # inputs of one sweep, resident in device memory
+        moves = []
+        for k in range(n_tot):
+            e = int(wl.moves.electron[k])
+            new_r = torch.as_tensor(wl.walkers.pos[:, e] + wl.moves.disp[k], device="cuda")
+            moves.append((e, ctx.sgauss_eval(ctx.spin_of(e), new_r.contiguous()),
+                          torch.as_tensor(wl.moves.accept_half[k], dtype=torch.uint8, device="cuda")))
+        outs = [(torch.empty(W, dtype=torch.float64, device="cuda"),
+                 torch.empty((W, 3), dtype=torch.float64, device="cuda"),
+                 torch.empty(W, dtype=torch.float64, device="cuda"),
+                 torch.zeros(W, dtype=torch.int32, device="cuda")) for _ in range(n_tot)]
+        if autotune:
+            up = next(m[1] for m in moves if m[0] < nu)
+            dn = next(m[1] for m in moves if m[0] >= nu)
+            ctx.autotune(up, dn)
+            ctx.init(ou, od)
+        plan = [ctx.get_plan(0), ctx.get_plan(1)]
+
+        def sweep():
+            for (e, no, mask), out in zip(moves, outs):
+                ctx.propose(e, no, out)
+                ctx.accept(e, mask)
+
+        # warmup graph and timed graph (K sweeps in one graph)
+        stream.synchronize()
+        with ctx.capture() as cw:
+            for _ in range(max(warmup, 1)):
+                sweep()
+        with ctx.capture() as ct:
+            for _ in range(steps):
+                sweep()
+        for _ in range(1 if warmup > 0 else 0):
+            cw.graph.launch()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        ct.graph.launch()
+        t1.record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        ms_total = t0.elapsed_time(t1)
+        # the same K sweeps once more, issued directly, with a HIP event pair
+        # around every launch of the determinant kernel (events recorded
+        # inside a graph carry no timestamps on this runtime)
+        ctx.profile_enable(steps * n_tot)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            sweep()
+        e1.record(stream)
+        stream.synchronize()
+        ms_eager = e0.elapsed_time(e1)
+        det_ms, det_n = ctx.profile_read()
+        ctx.profile_disable()
+        st = torch.stack([o[3] for o in outs]).cpu().numpy()
+    ms_step = ms_total / steps
+    wdets = W * s.n_det * n_tot
+    fl = np.mean([flops_per_launch(s.exc[ctx.spin_of(m[0])], W) for m in moves])
+    det_avg_s = det_ms / max(det_n, 1) / 1e3
+    return dict(precision=precision, ms_per_step=ms_step, value=wdets / (ms_step / 1e3),
+                ms_per_step_eager=ms_eager / steps,
+                det_launches=det_n, det_avg_us=det_avg_s * 1e6, det_flops_per_launch=fl,
+                det_tflops=fl / det_avg_s / 1e12 if det_n else None, plan=plan,
+                status_bits=int(np.bitwise_or.reduce(st.ravel())) if st.size else 0)
+
+
+def cpu_baseline(wl, target_seconds=12.0):
+    """The oracle on a bounded sample of the same workload (the first walkers,
+    the first moves of the sweep), on the host cores."""
+    import oracle
+    s = wl.system
+    threads = oracle.num_threads()
+    sample_w = min(wl.walkers.W, max(64, 32 * threads))
+    pos = wl.walkers.pos[:sample_w].copy()
+    n_tot = sum(s.n_elec)
+    moves = 0
+    t0 = time.perf_counter()
+    while True:
+        k = moves % n_tot
+        e = int(wl.moves.electron[k])
+        oracle.move(s, pos, e, pos[:, e] + wl.moves.disp[k, :sample_w])
+        moves += 1
+        if time.perf_counter() - t0 > target_seconds or moves >= n_tot:
+            break
+    dt = time.perf_counter() - t0
+    walkers_done = moves * sample_w
+    return dict(value=walkers_done * s.n_det / dt, unit="walker.det/s", cores=threads,
+                kind="oracle",
+                sample=f"{sample_w} walkers x {moves} moves of the same workload "
+                       f"(full-LU oracle, {dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--forms", default="fp64,mixed,mixed_gemm")
+    ap.add_argument("--walkers", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the walkers are "
+              "independent, so a multi-GPU run would shard them with no per-move "
+              "communication; this build measures the one-GPU share.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import synth
+    import paper_1106_2456_amd  # noqa: F401  (fails loudly without libmde.so)
+
+    wl = synth.water_like(2, W=args.walkers)
+    log(f"workload: W={wl.walkers.W} n_det={wl.system.n_det} U={wl.meta['n_exc_up']}/{wl.meta['n_exc_dn']}")
+    forms = {}
+    for f in [x for x in args.forms.split(",") if x]:
+        r = run_form(wl, f, args.steps, args.warmup, autotune=not args.no_autotune)
+        log(f"{f}: {r['ms_per_step']:.3f} ms/sweep  {r['value']:.3e} walker.det/s  "
+            f"det kernel {r['det_avg_us']:.1f} us ({r['det_tflops']:.2f} TFLOP/s) plan {r['plan'][0]}")
+        forms[f] = r
+    head = forms.get("fp64") or next(iter(forms.values()))
+    cpu = None if args.no_cpu else cpu_baseline(wl)
+    achieved = head["det_tflops"]
+    traffic = None
+    out = {
+        "metric": "excited-det ratios/s (walker.det, +grad/lap) mixed/batched vs plain FP64",
+        "value": head["value"],
+        "unit": "walker.det/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head["precision"] == "fp64" else "f32-table/f64",
+        "data": "synthetic (seeded s-Gaussian water-like system)",
+        "config": {"workload": "water-like batched: 5+5 electrons, 5+20 orbitals/spin, "
+                               "10000 determinants (orders 1-4), 4096 walkers, FP64; "
+                               "step = one sweep of 10 single-electron moves, 50% accepted",
+                   "walkers": wl.walkers.W, "n_det": wl.system.n_det,
+                   "moves_per_step": sum(wl.system.n_elec), "precision": head["precision"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                     "traffic": traffic, "kernel": "k_det<double, propose>",
+                     "launch_us": head["det_avg_us"],
+                     "flops_per_launch": head["det_flops_per_launch"]},
+        "cpu_baseline": cpu,
+        "forms": {k: {kk: v[kk] for kk in ("value", "ms_per_step", "ms_per_step_eager", "det_avg_us",
+                                           "det_tflops", "status_bits", "plan")}
+                  for k, v in forms.items()},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -210,6 +210,20 @@ mde_status mde_get_plan(const mde_ctx *ctx, int32_t spin, int32_t *walker_tile,
 mde_status mde_autotune(mde_ctx *ctx, const double *new_orb_up,
                         const double *new_orb_dn, const char *cache_path);
 
+/* ---- profiling ---------------------------------------------------------- */
+
+/* While enabled, every launch of the determinant kernel made by a proposal
+ * (mde_propose / mde_grad_lap) is bracketed by a pair of HIP events recorded
+ * on the context's stream -- inside captured graphs too, where each captured
+ * launch gets its own pair.  At most max_launches pairs are recorded; later
+ * launches are not bracketed.  Host-side objects only. */
+mde_status mde_profile_enable(mde_ctx *ctx, int32_t max_launches);
+/* After the caller has synchronised the stream: sum of the elapsed times of
+ * the recorded pairs (ms) and their number.  Pairs captured into a graph
+ * hold the times of that graph's last replay. */
+mde_status mde_profile_read(mde_ctx *ctx, double *total_ms, int32_t *count);
+mde_status mde_profile_disable(mde_ctx *ctx);
+
 /* ---- graphs ------------------------------------------------------------- */
 
 /* Capture every call made on ctx's stream between begin and end into a HIP

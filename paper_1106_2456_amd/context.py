@@ -247,6 +247,18 @@ class Context:
         cp = cache_path.encode() if cache_path else None
         self._chk(lib().mde_autotune(self._h, _ptr(new_orb_up), _ptr(new_orb_dn), cp), "autotune")
 
+    def profile_enable(self, max_launches: int):
+        self._chk(lib().mde_profile_enable(self._h, max_launches), "profile_enable")
+
+    def profile_read(self):
+        """(total ms, count) of the bracketed determinant-kernel launches."""
+        t, n = C.c_double(), C.c_int32()
+        self._chk(lib().mde_profile_read(self._h, C.byref(t), C.byref(n)), "profile_read")
+        return t.value, n.value
+
+    def profile_disable(self):
+        self._chk(lib().mde_profile_disable(self._h), "profile_disable")
+
     @contextmanager
     def capture(self):
         """with ctx.capture() as cap: ...calls...;  cap.graph.launch()"""

@@ -384,7 +384,7 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
     const int w = blockIdx.x;
     if (w >= I.W) return;
     const SpinDev &S = I.s[mv.spin];
-    const int n = S.n, m = S.m, no = S.no, row = mv.row, nmax = I.nmax, mmax = I.mmax;
+    const int n = S.n, m = S.m, no = S.no, row = mv.row, nmax = I.nmax;
     const int rows = n + 4;
     const int rp = (rows + 15) & ~15, kp = (n + 3) & ~3, mp = (m + 15) & ~15;
     const int lda = kp + 1;

@@ -102,6 +102,10 @@ struct mde_ctx {
     long accept_count = 0;
     bool capturing = false;
     const double *last_T[2] = {nullptr, nullptr};   // tables of the last mde_eval_tables
+    // profiling event pairs around determinant-kernel launches
+    std::vector<hipEvent_t> prof_ev;
+    int prof_used = 0;
+    bool prof_on = false;
     // plan fields chosen by the caller (kept when the default plan is applied)
     bool user_wt = false, user_thr[2] = {false, false}, user_item[2] = {false, false};
 };
@@ -537,6 +541,8 @@ static mde_status full_eval(mde_ctx *c, const double *orb_up, const double *orb_
     return MDE_OK;
 }
 
+static void prof_free(mde_ctx *c);
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -582,6 +588,7 @@ mde_status mde_create(const mde_desc *desc, void *hip_stream, mde_ctx **out) {
 }
 
 mde_status mde_destroy(mde_ctx *ctx) {
+    if (ctx) prof_free(ctx);
     delete ctx;
     return MDE_OK;
 }
@@ -882,10 +889,16 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
     MDE_HIP(c, launch_propose(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, nmax, mmax,
                               c->WT, c->h.s[s].n_tiles));
     SpinHost &sp = c->sp[s];
+    const bool prof = c->prof_on && 2 * (c->prof_used + 1) <= (int)c->prof_ev.size();
+    if (prof) MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream));
     if (!sp.items.empty())
         MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], (int)sp.items.size(), sp.ex_cap,
                               nullptr, m, DM_PROPOSE, c->d.precision, c->WT, sp.lds_prop, sp.threads,
                               sp.grid, c->h.counter, nullptr, nullptr));
+    if (prof) {
+        MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream));
+        c->prof_used++;
+    }
     MDE_HIP(c, launch_finish(c->stream, c->d_inst, 1, c->W, nullptr, m, c->h.counter));
     c->pending_e = e;
     return MDE_OK;
@@ -1109,6 +1122,46 @@ mde_status mde_autotune(mde_ctx *c, const double *new_orb_up, const double *new_
         f << key << " | " << best.WT << " " << best.item_exc[0] << " " << best.threads[0] << " "
           << best.item_exc[1] << " " << best.threads[1] << "\n";
     }
+    return MDE_OK;
+}
+
+// ---- profiling ----------------------------------------------------------------
+
+static void prof_free(mde_ctx *c) {
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    c->prof_ev.clear();
+    c->prof_used = 0;
+    c->prof_on = false;
+}
+
+mde_status mde_profile_enable(mde_ctx *c, int32_t max_launches) {
+    if (!c) return MDE_INVALID;
+    if (max_launches < 1 || max_launches > 1 << 16) MDE_FAIL(c, MDE_INVALID, "bad launch count");
+    if (c->capturing) MDE_FAIL(c, MDE_STATE, "enable profiling before capture");
+    prof_free(c);
+    c->prof_ev.resize(2 * (size_t)max_launches);
+    for (auto &e : c->prof_ev)
+        MDE_HIP(c, hipEventCreate(&e));
+    c->prof_on = true;
+    return MDE_OK;
+}
+
+mde_status mde_profile_read(mde_ctx *c, double *total_ms, int32_t *count) {
+    if (!c || !total_ms || !count) return MDE_INVALID;
+    double t = 0.0;
+    for (int i = 0; i < c->prof_used; ++i) {
+        float ms = 0.f;
+        MDE_HIP(c, hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]));
+        t += ms;
+    }
+    *total_ms = t;
+    *count = c->prof_used;
+    return MDE_OK;
+}
+
+mde_status mde_profile_disable(mde_ctx *c) {
+    if (!c) return MDE_INVALID;
+    prof_free(c);
     return MDE_OK;
 }
 
