@@ -468,25 +468,36 @@ hipError_t launch_precontract(hipStream_t st, const InstDev *d_inst, const InstD
 // log|Psi| = log|D0up| + log|D0dn| + log|N|.
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(1024)
-k_nsum(const InstDev *__restrict__ insts, double *log_abs_psi, double *sign_psi, int32_t *status,
-       int with_ref) {
+// phase 1: block (tile, part) sums u in part `part` of NSPLIT slices, fixed
+// order inside (slots) and across slots; phase 2 adds the NSPLIT partials
+__global__ void __launch_bounds__(256)
+k_nsum_part(const InstDev *__restrict__ insts) {
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[0];
-    const int WT = S.WT, t = blockIdx.x;
+    const int WT = S.WT, t = blockIdx.x, part = blockIdx.y;
     const int wl = threadIdx.x % WT, slot = threadIdx.x / WT, nslot = blockDim.x / WT;
+    const int uc = (S.U + NSPLIT - 1) / NSPLIT, u0 = part * uc, u1 = min(S.U, u0 + uc);
     const size_t base = (size_t)t * S.U * WT + wl;
     const auto Cb = MDE_G(double, S.C) + base;
     const auto Rb = MDE_G(double, S.R) + base;
     double s = 0.0;
-    for (int u = slot; u < S.U; u += nslot) s = fma(Cb[(size_t)u * WT], Rb[(size_t)u * WT], s);
-    __shared__ double red[1024];
+    for (int u = u0 + slot; u < u1; u += nslot) s = fma(Cb[(size_t)u * WT], Rb[(size_t)u * WT], s);
+    __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();
     if (slot != 0) return;
     for (int v = 1; v < nslot; ++v) s += red[v * WT + wl];
-    const int w = t * WT + wl;
+    MDE_GW(double, I.npart)[(size_t)part * S.n_tiles * WT + t * WT + wl] = s;
+}
+
+__global__ void k_nsum(const InstDev *__restrict__ insts, double *log_abs_psi, double *sign_psi,
+                       int32_t *status, int with_ref) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[0];
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= I.W) return;
+    double s = 0.0;
+    for (int p = 0; p < NSPLIT; ++p) s += MDE_G(double, I.npart)[(size_t)p * S.n_tiles * S.WT + w];
     I.Nold[w] = s;
     int bits = I.st[w];
     if (!(s != 0.0) || !isfinite(s)) bits |= 8;
@@ -505,9 +516,11 @@ k_nsum(const InstDev *__restrict__ insts, double *log_abs_psi, double *sign_psi,
 hipError_t launch_nsum(hipStream_t st, const InstDev *d_inst, const InstDev &h,
                        double *log_abs_psi, double *sign_psi, int32_t *status, int with_ref) {
     const SpinDev &S = h.s[0];
-    const int threads = S.WT >= 16 ? 1024 : 256;
-    hipLaunchKernelGGL(k_nsum, dim3(S.n_tiles), dim3(threads), 0, st, d_inst, log_abs_psi, sign_psi,
-                       status, with_ref);
+    hipLaunchKernelGGL(k_nsum_part, dim3(S.n_tiles, NSPLIT), dim3(256), 0, st, d_inst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_nsum, dim3((h.W + 63) / 64), dim3(64), 0, st, d_inst, log_abs_psi,
+                       sign_psi, status, with_ref);
     return hipGetLastError();
 }
 
@@ -560,7 +573,7 @@ __global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__re
 hipError_t launch_finish(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int32_t *counter) {
     (void)counter;
-    const int threads = 256;
+    const int threads = 64;
     hipLaunchKernelGGL(k_finish, dim3((maxW + threads - 1) / threads, n_inst), dim3(threads), 0, st,
                        d_insts, d_moves, m1);
     return hipGetLastError();

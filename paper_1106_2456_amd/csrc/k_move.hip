@@ -194,14 +194,17 @@ hipError_t launch_table_gemm(hipStream_t st, const InstDev *d_inst, const InstDe
 
 // TT = double: FP64 tables.  TT = float (MIXED): FP32 table storage, every
 // product and the rank-one update in FP64, results rounded once to FP32.
+// Blocks: (walker tile, part) x instance; part `part` of `split` handles a
+// slice of the virtual orbitals; part 0 also writes the per-walker scalars.
 template <int WT, typename TT>
 __global__ void __launch_bounds__(1024)
-k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1) {
+k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1,
+            int split) {
     const int inst = blockIdx.y;
     const InstDev &I = insts[inst];
     const MoveArgs mv = moves ? moves[inst] : m1;
     const SpinDev &S = I.s[mv.spin];
-    const int t = blockIdx.x;
+    const int t = blockIdx.x / split, part = blockIdx.x % split;
     if (t >= S.n_tiles) return;
     const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nm = n * m;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -233,6 +236,20 @@ k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ move
         d_s[3 * n * WT + idx] = d3;
     }
     __syncthreads();
+    if (part == 0) {
+        // row of the commit's rank-one update: a'^T A^-1 - e_i^T
+        const auto rr = MDE_GW(double, I.rrow) + (size_t)t * n * WT;
+        for (int idx = tid; idx < n * WT; idx += nthr) {
+            const int j = idx / WT, l = idx % WT, w = t * WT + l;
+            double r = 0.0;
+            if (w < W) {
+                const auto Bw = B + (size_t)w * n * n;
+                for (int k = 0; k < n; ++k) r = fma(a_s[k * WT + l], Bw[(size_t)k * n + j], r);
+                r -= (j == row) ? 1.0 : 0.0;
+            }
+            rr[idx] = r;
+        }
+    }
     if (tid < WT) {
         const int l = tid, w = t * WT + l;
         double rho = 0.0, dc[4] = {0, 0, 0, 0};
@@ -246,7 +263,7 @@ k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ move
         ir_s[l] = irho;
 #pragma unroll
         for (int a = 0; a < 4; ++a) rA_s[a * WT + l] = dc[a] * irho;
-        if (w < W) {
+        if (w < W && part == 0) {
             I.rho[w] = rho;
 #pragma unroll
             for (int a = 0; a < 4; ++a) I.rhoA[(size_t)w * 4 + a] = dc[a] * irho;
@@ -263,12 +280,15 @@ k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ move
     // the determinant kernel
     const auto cpd = MDE_GW(double, I.cp) + (size_t)t * n * WT;
     const auto cpt = MDE_GW(TT, f64 ? (void *)I.cp : (void *)I.cp32) + (size_t)t * n * WT;
-    for (int idx = tid; idx < n * WT; idx += nthr) {
-        const double v = c_s[idx] * ir_s[idx % WT];
-        cpd[idx] = v;
-        if (!f64) cpt[idx] = (TT)v;
+    if (part == 0) {
+        for (int idx = tid; idx < n * WT; idx += nthr) {
+            const double v = c_s[idx] * ir_s[idx % WT];
+            cpd[idx] = v;
+            if (!f64) cpt[idx] = (TT)v;
+        }
     }
-    for (int idx = tid; idx < m * WT; idx += nthr) {
+    const int mc = (m + split - 1) / split, p0 = part * mc, p1 = min(m, p0 + mc);
+    for (int idx = p0 * WT + tid; idx < p1 * WT; idx += nthr) {
         const int p = idx / WT, l = idx % WT, w = t * WT + l;
         double v = 0.0, wa[4] = {0, 0, 0, 0};
         for (int r = 0; r < n; ++r) {
@@ -294,7 +314,8 @@ k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ move
             Tpt[o] = (TT)fma(-c_s[r * WT + l], qi, (double)Tt[o]);
         }
     }
-    for (int idx = tid; idx < no * WT; idx += nthr) {
+    const int nc = (no + split - 1) / split, q0 = part * nc, q1 = min(no, q0 + nc);
+    for (int idx = q0 * WT + tid; idx < q1 * WT; idx += nthr) {
         const int p = idx / WT, l = idx % WT, w = t * WT + l;
         if (w < W) I.newrow[(size_t)w * I.nomax + p] = orb[(size_t)w * 5 * no + p];
     }
@@ -361,6 +382,7 @@ k_propose_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ 
             for (int a = 0; a < 4; ++a) f[a] = fma(nr[(1 + a) * no + k], b, f[a]);
         }
         const double rd = r - (j == row ? 1.0 : 0.0);
+        I.rrow[((size_t)(w / S.WT) * n + j) * S.WT + (w % S.WT)] = rd;
         for (int rr = 0; rr < n; ++rr) {
             const double cpr = Bw[(size_t)rr * n + row] * irho;
             Ap[(size_t)rr * nmax + j] = (float)fma(-cpr, rd, Bw[(size_t)rr * n + j]);
@@ -441,19 +463,19 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
 
 hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                           const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
-                          int mmax, int WT, int max_tiles) {
+                          int mmax, int WT, int max_tiles, int split) {
     if (prec == 0 || prec == 1) {
-        const int threads = WT >= 16 ? 1024 : 256;
+        const int threads = (WT >= 16 && split == 1) ? 1024 : 256;
         const size_t lds = sizeof(double) * ((size_t)6 * nmax * WT + 5 * WT);
-        dim3 g(max_tiles, n_inst);
+        dim3 g(max_tiles * split, n_inst);
 #define MDE_PP(X)                                                                                \
     case X:                                                                                      \
         if (prec == 0) {                                                                         \
             hipLaunchKernelGGL((k_propose64<X, double>), g, dim3(threads), lds, st, d_insts,    \
-                               d_moves, m1);                                                     \
+                               d_moves, m1, split);                                              \
         } else {                                                                                 \
             hipLaunchKernelGGL((k_propose64<X, float>), g, dim3(threads), lds, st, d_insts,     \
-                               d_moves, m1);                                                     \
+                               d_moves, m1, split);                                              \
         }                                                                                        \
         break;
         switch (WT) {
@@ -483,19 +505,17 @@ hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, in
 // ---------------------------------------------------------------------------
 
 template <int WT>
-__global__ void __launch_bounds__(1024)
-k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1) {
+__global__ void __launch_bounds__(256)
+k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1,
+         int split) {
     const int inst = blockIdx.y;
     const InstDev &I = insts[inst];
     const MoveArgs mv = moves ? moves[inst] : m1;
     const SpinDev &S = I.s[mv.spin];
-    const int t = blockIdx.x;
+    const int t = blockIdx.x / split, part = blockIdx.x % split;
     if (t >= S.n_tiles) return;
     const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nm = n * m;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    extern __shared__ double sha[];
-    double *rs = sha;              // [n][WT]  a'^T A^-1 - e_i^T
-    double *cps = rs + n * WT;     // [n][WT]  c'
     __shared__ int acc_s[64];
     if (tid < WT) {
         const int w = t * WT + tid;
@@ -503,46 +523,35 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
     }
     __syncthreads();
     const auto nrow = MDE_G(double, I.newrow);
-    for (int idx = tid; idx < n * WT; idx += nthr) {
-        const int j = idx / WT, l = idx % WT, w = t * WT + l;
-        double r = 0.0, c = 0.0;
-        if (acc_s[l]) {
-            const auto Bw = MDE_G(double, S.B) + (size_t)w * n * n;
-            const auto nr = nrow + (size_t)w * I.nomax;
-            for (int k = 0; k < n; ++k) r = fma(nr[k], Bw[(size_t)k * n + j], r);
-            r -= (j == row) ? 1.0 : 0.0;
-            c = MDE_G(double, I.cp)[((size_t)t * n + j) * WT + l];
-        }
-        rs[idx] = r;
-        cps[idx] = c;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < n * n * WT; idx += nthr) {
+    const auto rr = MDE_G(double, I.rrow) + (size_t)t * n * WT;
+    const auto cp = MDE_G(double, I.cp) + (size_t)t * n * WT;
+    // A^-1 rows of this part (the update row a'^T A^-1 - e_i^T was formed
+    // from the pre-update inverse by the proposal)
+    const int rc = (n + split - 1) / split, r0 = part * rc, r1 = min(n, r0 + rc);
+    for (int idx = r0 * n * WT + tid; idx < r1 * n * WT; idx += nthr) {
         const int l = idx % WT, rj = idx / WT, r = rj / n, j = rj - r * n;
         if (!acc_s[l]) continue;
         const size_t o = ((size_t)(t * WT + l) * n + r) * n + j;
-        S.B[o] = fma(-cps[r * WT + l], rs[j * WT + l], S.B[o]);
+        S.B[o] = fma(-cp[r * WT + l], rr[j * WT + l], S.B[o]);
     }
     const size_t tb = (size_t)t * nm * WT;
+    const int ec = (nm * WT + split - 1) / split, e0 = part * ec, e1 = min(nm * WT, e0 + ec);
     if (I.prec == 0) {
-        for (int idx = tid; idx < nm * WT; idx += nthr)
+        for (int idx = e0 + tid; idx < e1; idx += nthr)
             if (acc_s[idx % WT]) S.T[tb + idx] = I.Tp[tb + idx];
     } else {
-        for (int idx = tid; idx < nm * WT; idx += nthr)
+        for (int idx = e0 + tid; idx < e1; idx += nthr)
             if (acc_s[idx % WT]) S.T32[tb + idx] = I.Tp32[tb + idx];
-        if (I.prec == 2) {
-            for (int idx = tid; idx < m * WT; idx += nthr) {
-                const int p = idx / WT, l = idx % WT, w = t * WT + l;
-                if (acc_s[l])
-                    S.PhiV32[((size_t)w * n + row) * m + p] = (float)nrow[(size_t)w * I.nomax + n + p];
-            }
-        }
     }
-    for (int idx = tid; idx < no * WT; idx += nthr) {
+    const int nc = (no + split - 1) / split, q0 = part * nc, q1 = min(no, q0 + nc);
+    for (int idx = q0 * WT + tid; idx < q1 * WT; idx += nthr) {
         const int p = idx / WT, l = idx % WT, w = t * WT + l;
-        if (acc_s[l]) S.Phi[((size_t)w * n + row) * no + p] = nrow[(size_t)w * I.nomax + p];
+        if (!acc_s[l]) continue;
+        const double v = nrow[(size_t)w * I.nomax + p];
+        S.Phi[((size_t)w * n + row) * no + p] = v;
+        if (I.prec == 2 && p >= n) S.PhiV32[((size_t)w * n + row) * m + (p - n)] = (float)v;
     }
-    if (tid < WT && acc_s[tid]) {
+    if (part == 0 && tid < WT && acc_s[tid]) {
         const int w = t * WT + tid;
         const double rho = I.rho[w];
         S.logdet[w] += log(fabs(rho));
@@ -553,14 +562,12 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
 
 hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
-                         int mmax, int WT, int max_tiles) {
-    (void)prec; (void)mmax; (void)maxW;
-    const int threads = WT >= 16 ? 1024 : 256;
-    const size_t lds = sizeof(double) * 2 * (size_t)nmax * WT;
-    dim3 g(max_tiles, n_inst);
-#define MDE_AC(X)                                                                           \
-    case X:                                                                                 \
-        hipLaunchKernelGGL(k_accept<X>, g, dim3(threads), lds, st, d_insts, d_moves, m1);  \
+                         int mmax, int WT, int max_tiles, int split) {
+    (void)prec; (void)mmax; (void)maxW; (void)nmax;
+    dim3 g(max_tiles * split, n_inst);
+#define MDE_AC(X)                                                                              \
+    case X:                                                                                    \
+        hipLaunchKernelGGL(k_accept<X>, g, dim3(256), 0, st, d_insts, d_moves, m1, split);    \
         break;
     switch (WT) {
         MDE_AC(1) MDE_AC(2) MDE_AC(4) MDE_AC(8) MDE_AC(16) MDE_AC(32) MDE_AC(64)

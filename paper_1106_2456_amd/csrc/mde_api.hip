@@ -416,6 +416,8 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
     h.cp = cv.take<double>(Wq * nmax);
     h.Tp = prec == 0 ? cv.take<double>(Wq * nmax * mmax) : nullptr;
     h.rhoA = cv.take<double>((size_t)W * 4);
+    h.rrow = cv.take<double>(Wq * nmax);
+    h.npart = cv.take<double>(Wq * NSPLIT);
     h.g = prec == 0 ? cv.take<double>(Wq * 4 * mmax) : nullptr;
     h.newrow = cv.take<double>((size_t)W * nomax);
     h.g32 = prec != 0 ? cv.take<float>(Wq * 4 * mmax) : nullptr;
@@ -482,6 +484,14 @@ static mde_status apply_plan(mde_ctx *c) {
 // ---------------------------------------------------------------------------
 // state maintenance
 // ---------------------------------------------------------------------------
+
+// parts per walker tile of the per-walker kernels: enough blocks to cover
+// the CUs twice, at most `cap` (rows or columns) and 16
+static int row_split(int n_cu, int blocks, int cap) {
+    int s = (2 * n_cu + blocks - 1) / std::max(blocks, 1);
+    s = std::min(s, std::min(std::max(cap, 1), 16));
+    return std::max(s, 1);
+}
 
 static MoveArgs no_move() {
     MoveArgs m{};
@@ -887,7 +897,8 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
     m.status = status;
     const int nmax = c->h.nmax, mmax = c->h.mmax;
     MDE_HIP(c, launch_propose(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, nmax, mmax,
-                              c->WT, c->h.s[s].n_tiles));
+                              c->WT, c->h.s[s].n_tiles,
+                              row_split(c->n_cu, c->h.s[s].n_tiles, c->sp[s].m)));
     SpinHost &sp = c->sp[s];
     const bool prof = c->prof_on && 2 * (c->prof_used + 1) <= (int)c->prof_ev.size();
     if (prof) MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream));
@@ -927,7 +938,8 @@ mde_status mde_accept(mde_ctx *c, int32_t e, const uint8_t *accept) {
     m.row = row;
     m.accept = accept;
     MDE_HIP(c, launch_accept(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, c->h.nmax,
-                             c->h.mmax, c->WT, c->h.s[s].n_tiles));
+                             c->h.mmax, c->WT, c->h.s[s].n_tiles,
+                             row_split(c->n_cu, c->h.s[s].n_tiles, c->sp[s].n)));
     c->R_valid[s] = false;
     c->C_valid[1 - s] = false;
     c->pending_e = -1;
@@ -1424,8 +1436,9 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const
     mde_status st = group_upload(g);
     if (st) return st;
     const MoveArgs none = no_move();
+    const int gt = (g->maxW + g->WT - 1) / g->WT;
     if (launch_propose(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, g->prec, g->nmax,
-                       g->mmax, g->WT, (g->maxW + g->WT - 1) / g->WT) != hipSuccess)
+                       g->mmax, g->WT, gt, row_split(g->ctx[0]->n_cu, gt * n, g->mmax)) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "propose launch");
     if (launch_det(g->stream, g->d_insts, n, g->d_items, g->n_items, g->ex_cap, g->d_moves, none,
                    DM_PROPOSE, g->prec, g->WT, g->lds, g->threads, g->grid, g->ctx[0]->h.counter,
@@ -1455,8 +1468,9 @@ mde_status mde_group_accept(mde_group *g, const int32_t *e, const uint8_t *const
     mde_status st = group_upload(g);
     if (st) return st;
     const MoveArgs none = no_move();
+    const int gt = (g->maxW + g->WT - 1) / g->WT;
     if (launch_accept(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, g->prec, g->nmax,
-                      g->mmax, g->WT, (g->maxW + g->WT - 1) / g->WT) != hipSuccess)
+                      g->mmax, g->WT, gt, row_split(g->ctx[0]->n_cu, gt * n, g->nmax)) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "accept launch");
     for (int i = 0; i < n; ++i) {
         mde_ctx *c = g->ctx[i];

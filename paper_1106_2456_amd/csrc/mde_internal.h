@@ -68,6 +68,8 @@ struct InstDev {
     double *Tp;      // tiled [n*m]  T'_V (FP64 mode)
     double *g;       // tiled [4*m]  g^a (FP64 mode)
     double *rhoA;    // [W][4] rho^a
+    double *rrow;    // tiled [n]    a'^T A^-1 - e_i^T (for the commit)
+    double *npart;   // [NSPLIT][n_tiles*WT] partial N sums
     double *newrow;  // [W][nomax] proposed orbital values of the moved electron
     float *g32;      // tiled [4*m] (mixed)
     float *cp32;     // tiled [n] (mixed)
@@ -107,7 +109,7 @@ hipError_t launch_table_gemm(hipStream_t st, const InstDev *d_inst, const InstDe
                              int spin);
 hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                           const MoveArgs *d_moves, const MoveArgs &m1, int prec,
-                          int nmax, int mmax, int WT, int max_tiles);
+                          int nmax, int mmax, int WT, int max_tiles, int split);
 hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst,
                       const WorkItem *items, int n_items, int ex_cap,
                       const MoveArgs *d_moves, const MoveArgs &m1, int mode, int prec,
@@ -117,7 +119,8 @@ hipError_t launch_finish(hipStream_t st, const InstDev *d_insts, int n_inst, int
                          const MoveArgs *d_moves, const MoveArgs &m1, int32_t *counter);
 hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int prec,
-                         int nmax, int mmax, int WT, int max_tiles);
+                         int nmax, int mmax, int WT, int max_tiles, int split);
+constexpr int NSPLIT = 16;   // parts of the excitation range in the N sum
 hipError_t launch_precontract(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
                               int spin, const double *coef);
 hipError_t launch_coef_gather(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
