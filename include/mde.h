@@ -65,10 +65,11 @@ typedef enum {
                              Sherman-Morrison table update, the small
                              determinants, LU, denominators and CI sums are
                              computed in FP64                                 */
-    MDE_MIXED_GEMM = 2    /* as MDE_MIXED, but every proposal rebuilds the
-                             table with one FP32 MFMA GEMM T' = A'^-1 Phi'_V
-                             (Algorithm 1 step 3); its error grows with the
-                             condition number of the reference matrix         */
+    MDE_MIXED_GEMM = 2    /* as MDE_MIXED, but every accepted move rebuilds
+                             the table with one FP32 MFMA GEMM
+                             T = A^-1 Phi_V (Algorithm 1 step 3) instead of
+                             the rank-one update; its error grows with the
+                             condition number of the reference matrix       */
 } mde_precision;
 
 /* per-walker status bits */
@@ -151,7 +152,12 @@ mde_status mde_refresh(mde_ctx *ctx, double *log_abs_psi, double *sign_psi,
 /* Proposal for electron e moving to r_e' (Algorithm 1; Sec. IV-A):
  * new_orb [W][5][n_orb_sigma(e)] is that electron's orbital block at r_e'.
  * Outputs ratio[W] = Psi(R')/Psi(R), grad[W][3] = grad_e ln Psi(R'),
- * lap[W] = lap_e Psi(R')/Psi(R').  State is unchanged until mde_accept. */
+ * lap[W] = lap_e Psi(R')/Psi(R').  The excited determinants at R' are read
+ * from the current table through the matrix determinant lemma (the updated
+ * table of Sec. III is formed only on acceptance), so no intermediate is
+ * divided by det A'/det A; the outputs stay finite on the reference
+ * determinant's node (MDE_ST_SMALL_RATIO then marks a move whose commit
+ * would be singular).  State is unchanged until mde_accept. */
 mde_status mde_propose(mde_ctx *ctx, int32_t e, const double *new_orb,
                        double *ratio, double *grad, double *lap, int32_t *status);
 

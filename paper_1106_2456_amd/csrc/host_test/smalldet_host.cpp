@@ -31,3 +31,37 @@ extern "C" double mde_host_small_det_generic(int k, const double *S, const doubl
     for (int j = 0; j < k; ++j) y[j] = yy[j];
     return det;
 }
+
+// Run form: det S and y from the prefix cofactors (first k-1 columns of S)
+// applied to the last column; S row-major k x k, k = 1..4.
+template <int K>
+static double run_form(const double *S, const double *c, double *y) {
+    constexpr int KQ = K > 1 ? K - 1 : 1;
+    double P[KQ][K], b[K], cc[K], u[K], v[KQ][K], ylast;
+    for (int j = 0; j < K - 1; ++j)
+        for (int r = 0; r < K; ++r) P[j][r] = S[r * K + j];
+    for (int r = 0; r < K; ++r) {
+        b[r] = S[r * K + K - 1];
+        cc[r] = c[r];
+    }
+    mde::prefix_cofactors<K, double>(P, cc, u, v, ylast);
+    double det = 0.0;
+    for (int r = 0; r < K; ++r) det += u[r] * b[r];
+    for (int j = 0; j < K - 1; ++j) {
+        double s = 0.0;
+        for (int r = 0; r < K; ++r) s += v[j][r] * b[r];
+        y[j] = s;
+    }
+    y[K - 1] = ylast;
+    return det;
+}
+
+extern "C" double mde_host_run_form(int k, const double *S, const double *c, double *y) {
+    switch (k) {
+        case 1: return run_form<1>(S, c, y);
+        case 2: return run_form<2>(S, c, y);
+        case 3: return run_form<3>(S, c, y);
+        case 4: return run_form<4>(S, c, y);
+        default: return 0.0;
+    }
+}

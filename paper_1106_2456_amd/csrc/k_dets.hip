@@ -22,20 +22,28 @@ __device__ __forceinline__ int exc_byte(const uint4 &x, int i) {
 // ---------------------------------------------------------------------------
 // persistent determinant kernel
 // ---------------------------------------------------------------------------
+//
+// Sums formed per walker over the moving spin's excitations u > 0, with
+// S_u = Tab[h][p] and y = adj(S_u) c[h]:
+//   acc[0]   = sum_u C_u det S_u
+//   acc[1+b] = sum_u C_u sum_j e^b[p_j] y_j,   b < NE
+// FP64 form (NE = 5): Tab = T, the current table, c = A^-1 e_i and
+// e = (q, w^x, w^y, w^z, w^L); k_finish forms rho N' = rho N - acc[1] and
+// rho sum_u C_u G^a_u = kappa^a N + acc[2+a].  Mixed forms (NE = 4): Tab = T',
+// the updated table, c = c', e = g^a; k_finish forms N' = C_0 + acc[0] and
+// sum_u C_u G^a_u = (kappa^a / rho) N' + acc[1+a].  (Matrix determinant
+// lemma and the bordered form; the reference excitation adds C_0 to N.)
+//
+// LDS rows: Tab[h][p] at entry h*m + p, e^b[p] at entry NE*p + b (the
+// components of one particle are consecutive rows), c[h] at entry h.
 
-// One order-K excitation for walker-lane wl.  PROPOSE: accumulate
-// C_u * (R_u, G^x_u, G^y_u, G^z_u, G^L_u) with
-//   R_u = det S,  G^a_u = rho^a R_u + sum_j g^a[p_j] y_j,  y = adj(S) c'[h].
-// VALUES: return det S.  Table entries are stored as TT (FP64, or FP32 in
-// the mixed form); the small-determinant arithmetic is always FP64 (in the
-// mixed form FP32 arithmetic lost up to 1e-3 on triples and quadruples
-// through cancellation, FP64 arithmetic on the FP32 entries keeps the
-// table's own accuracy).
+// One order-K excitation for walker-lane wl, all K x K entries gathered
+// (walker tiles below 64, where the lanes of a wave hold different
+// excitations).  PROPOSE accumulates into acc; VALUES returns det S.
 template <int K, typename TT, int MODE>
 __device__ __forceinline__ double det_one(const uint4 &ex, const TT *__restrict__ tabs,
                                           const TT *__restrict__ gs, const TT *__restrict__ cs,
-                                          int m, int WTP, int wl, const double rhoA[4],
-                                          double Cu, double acc[NSUM]) {
+                                          int m, int WTP, int wl, double Cu, double acc[NSUM]) {
     int h[K], hm[K], p[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -58,13 +66,13 @@ __device__ __forceinline__ double det_one(const uint4 &ex, const TT *__restrict_
     for (int r = 0; r < K; ++r) c[r] = (double)cs[h[r] * WTP + wl];
     const double dd = SmallDet<K, double>::run(col, c, y);
     acc[0] = fma(Cu, dd, acc[0]);
+    constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        double s = 0.0;
+    for (int j = 0; j < K; ++j) {
+        const double wy = Cu * y[j];
 #pragma unroll
-        for (int j = 0; j < K; ++j) s = fma((double)gs[(a * m + p[j]) * WTP + wl], y[j], s);
-        const double G = fma(rhoA[a], dd, s);
-        acc[1 + a] = fma(Cu, G, acc[1 + a]);
+        for (int b = 0; b < NE; ++b)
+            acc[1 + b] = fma((double)gs[(p[j] * NE + b) * WTP + wl], wy, acc[1 + b]);
     }
     return dd;
 }
@@ -72,8 +80,7 @@ __device__ __forceinline__ double det_one(const uint4 &ex, const TT *__restrict_
 template <typename TT, int MODE>
 __device__ double det_one_generic(int k, const uint4 &ex, const TT *__restrict__ tabs,
                                   const TT *__restrict__ gs, const TT *__restrict__ cs, int m,
-                                  int WTP, int wl, const double rhoA[4], double Cu,
-                                  double acc[NSUM]) {
+                                  int WTP, int wl, double Cu, double acc[NSUM]) {
     int h[MAXK], p[MAXK];
     for (int j = 0; j < k; ++j) {
         h[j] = exc_byte(ex, j);
@@ -86,50 +93,179 @@ __device__ double det_one_generic(int k, const uint4 &ex, const TT *__restrict__
     const double dd = small_det_generic<double>(k, col, c, y);
     if (MODE == DM_VALUES) return dd;
     acc[0] = fma(Cu, dd, acc[0]);
-    for (int a = 0; a < 4; ++a) {
-        double s = 0.0;
-        for (int j = 0; j < k; ++j) s = fma((double)gs[(a * m + p[j]) * WTP + wl], y[j], s);
-        const double G = fma(rhoA[a], dd, s);
-        acc[1 + a] = fma(Cu, G, acc[1 + a]);
+    constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
+    for (int j = 0; j < k; ++j) {
+        const double wy = Cu * y[j];
+        for (int b = 0; b < NE; ++b)
+            acc[1 + b] = fma((double)gs[(p[j] * NE + b) * WTP + wl], wy, acc[1 + b]);
     }
     return dd;
 }
 
-// Loop over the item's excitations; the CI weight of the next excitation is
-// loaded while the current one is evaluated.
+// Loop over the item's excitations (slot-strided); the CI weight of the next
+// excitation is loaded while the current one is evaluated.
 template <int K, typename TT, int MODE, int WT>
 __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
                                          const uint4 *__restrict__ exl, const TT *tabs,
                                          const TT *gs, const TT *cs, int wl, int slot, int nslot,
-                                         const double rhoA[4], double acc[NSUM]) {
+                                         double acc[NSUM]) {
     const int len = it.u1 - it.u0;
     const size_t base = ((size_t)it.tile * S.U + it.u0) * WT;
     const auto Cb = MDE_G(double, S.C) + base;
     const auto Rb = MDE_GW(double, S.R) + base;
     const int m = S.m, WTP = S.WTP;
     int j = slot;
-    if (WT == 64) j = __builtin_amdgcn_readfirstlane(j);
     double Cn = 0.0;
     if (MODE == DM_PROPOSE && j < len) Cn = Cb[(size_t)j * WT + wl];
     for (; j < len; j += nslot) {
-        uint4 ex = exl[j];
-        if (WT == 64) {
-            // one excitation per wave: keep its indices (and all gather
-            // address arithmetic) in scalar registers
-            ex.x = __builtin_amdgcn_readfirstlane(ex.x);
-            ex.y = __builtin_amdgcn_readfirstlane(ex.y);
-            ex.z = __builtin_amdgcn_readfirstlane(ex.z);
-            ex.w = __builtin_amdgcn_readfirstlane(ex.w);
-        }
+        const uint4 ex = exl[j];
         const double Cu = Cn;
         if (MODE == DM_PROPOSE && j + nslot < len) Cn = Cb[(size_t)(j + nslot) * WT + wl];
         double R;
         if (K > 0)
-            R = det_one<(K > 0 ? K : 1), TT, MODE>(ex, tabs, gs, cs, m, WTP, wl, rhoA, Cu, acc);
+            R = det_one<(K > 0 ? K : 1), TT, MODE>(ex, tabs, gs, cs, m, WTP, wl, Cu, acc);
         else
-            R = det_one_generic<TT, MODE>(it.order, ex, tabs, gs, cs, m, WTP, wl, rhoA, Cu, acc);
+            R = det_one_generic<TT, MODE>(it.order, ex, tabs, gs, cs, m, WTP, wl, Cu, acc);
         if (MODE == DM_VALUES) Rb[(size_t)j * WT + wl] = R;
     }
+}
+
+// ---- walker tile 64: one excitation per wave, evaluated in runs ----------
+//
+// The lanes of a wave are 64 walkers and every index is wave-uniform: the
+// records are read through the scalar cache and all control flow is scalar.
+// Excitations are sorted by holes, then particles, so consecutive
+// excitations of one order share their holes h_0..h_{K-1} and, often, their
+// first K-1 particles (the prefix).  Within such a run only the last column
+// b = T'[h][q] of S changes, and everything else is linear in b:
+//   det S = u . b,                 u = cofactors of the last column
+//   y_j   = v_j . b   (j < K-1),   v_j = the same with column j -> c'[h]
+//   y_{K-1} = u . c'[h]            (constant over the run)
+// so per excitation the wave gathers K table entries and the NE values e^b[q],
+// and the run accumulates
+//   Nrun += C det S,  Yrun_j += C y_j,  Zrun^b += C e^b[q];
+// on closing the run
+//   acc[0] += Nrun,  acc[1+b] += y_{K-1} Zrun^b + sum_j e^b[p_j] Yrun_j.
+
+#define MDE_K(T, p) ((const T __attribute__((address_space(4))) *)(p))
+
+__device__ __forceinline__ int byte_of(uint32_t w, int i) { return (int)((w >> (8 * i)) & 0xffu); }
+
+template <int K, typename TT, int MODE>
+__device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, int j1,
+                                           const TT *__restrict__ tabs, const TT *__restrict__ gs,
+                                           const TT *__restrict__ cs, int wl, double acc[NSUM]) {
+    constexpr int KP = K - 1;                  // prefix length
+    constexpr int KQ = KP > 0 ? KP : 1;
+    constexpr uint32_t PMASK = KP == 0 ? 0u : (KP >= 4 ? 0xffffffffu : ((1u << (8 * KP)) - 1u));
+    constexpr int WTP = 65;
+    constexpr int D = 4;                       // CI weights loaded ahead
+    constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
+    const int m = S.m;
+    const auto exr = MDE_K(uint32_t, S.ex);   // words x (holes 0..3), z (particles 0..3)
+    const size_t cb0 = (size_t)tile * S.U * 64 + wl;
+    const auto Cg = MDE_G(double, S.C) + cb0;
+    const auto Rg = MDE_GW(double, S.R) + cb0;
+    bool open = false;
+    uint32_t hx = 0, pz = 0;
+    int rb[K];
+    double c[K], u[K], v[KQ][K];
+    double ylast = 0.0, Nrun = 0.0, Yrun[KQ], Zrun[NE];
+#pragma unroll
+    for (int r = 0; r < K; ++r) { rb[r] = 0; c[r] = 0.0; u[r] = 0.0; }
+#pragma unroll
+    for (int j = 0; j < KQ; ++j) {
+        Yrun[j] = 0.0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) v[j][r] = 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < NE; ++b) Zrun[b] = 0.0;
+
+    auto close_run = [&]() {
+        acc[0] += Nrun;
+#pragma unroll
+        for (int b = 0; b < NE; ++b) {
+            double s = ylast * Zrun[b];
+#pragma unroll
+            for (int j = 0; j < KP; ++j)
+                s = fma((double)gs[(byte_of(pz, j) * NE + b) * WTP + wl], Yrun[j], s);
+            acc[1 + b] += s;
+        }
+    };
+
+    auto step = [&](const uint32_t hw, const uint32_t pw, double Cu, int j) {
+        const bool new_holes = !open || hw != hx;
+        if (new_holes || ((pw ^ pz) & PMASK) != 0u) {
+            if (MODE == DM_PROPOSE && open) close_run();
+            if (new_holes) {
+                hx = hw;
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    const int h = byte_of(hw, r);
+                    rb[r] = h * m;
+                    if (MODE == DM_PROPOSE) c[r] = (double)cs[h * WTP + wl];
+                }
+            }
+            pz = pw;
+            double P[KQ][K];
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                const int p = byte_of(pw, j);
+#pragma unroll
+                for (int r = 0; r < K; ++r) P[j][r] = (double)tabs[(rb[r] + p) * WTP + wl];
+            }
+            if (MODE == DM_PROPOSE) {
+                prefix_cofactors<K, double>(P, c, u, v, ylast);
+                Nrun = 0.0;
+#pragma unroll
+                for (int i = 0; i < KQ; ++i) Yrun[i] = 0.0;
+#pragma unroll
+                for (int b = 0; b < NE; ++b) Zrun[b] = 0.0;
+            }
+            else
+                last_cofactors<K, double>(P, u);
+            open = true;
+        }
+        const int q = byte_of(pw, KP);
+        double b[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) b[r] = (double)tabs[(rb[r] + q) * WTP + wl];
+        double det = 0.0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) det = fma(u[r], b[r], det);
+        if (MODE == DM_VALUES) {
+            Rg[(size_t)j * 64] = det;
+            return;
+        }
+        Nrun = fma(Cu, det, Nrun);
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+            double y = 0.0;
+#pragma unroll
+            for (int r = 0; r < K; ++r) y = fma(v[i][r], b[r], y);
+            Yrun[i] = fma(Cu, y, Yrun[i]);
+        }
+#pragma unroll
+        for (int b = 0; b < NE; ++b) Zrun[b] = fma(Cu, (double)gs[(q * NE + b) * WTP + wl], Zrun[b]);
+    };
+
+    double cb[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+        cb[i] = (MODE == DM_PROPOSE && j0 + i < j1) ? Cg[(size_t)(j0 + i) * 64] : 0.0;
+    for (int j = j0; j < j1; j += D) {
+        double cn[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            cn[i] = (MODE == DM_PROPOSE && j + D + i < j1) ? Cg[(size_t)(j + D + i) * 64] : 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            if (j + i < j1) step(exr[4 * (j + i)], exr[4 * (j + i) + 2], cb[i], j + i);
+#pragma unroll
+        for (int i = 0; i < D; ++i) cb[i] = cn[i];
+    }
+    if (MODE == DM_PROPOSE && open) close_run();
 }
 
 template <typename TT, int MODE, int WT>
@@ -152,7 +288,14 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
         const int gi = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (gi >= n_items) break;
-        const WorkItem it = items[gi];
+        WorkItem it = items[gi];
+        it.inst = __builtin_amdgcn_readfirstlane(it.inst);
+        it.spin = __builtin_amdgcn_readfirstlane(it.spin);
+        it.tile = __builtin_amdgcn_readfirstlane(it.tile);
+        it.order = __builtin_amdgcn_readfirstlane(it.order);
+        it.u0 = __builtin_amdgcn_readfirstlane(it.u0);
+        it.u1 = __builtin_amdgcn_readfirstlane(it.u1);
+        it.slot = __builtin_amdgcn_readfirstlane(it.slot);
         const InstDev &I = insts[it.inst];
         const SpinDev &S = I.s[it.spin];
         if (MODE == DM_PROPOSE) {
@@ -161,39 +304,41 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
         }
         const int n = S.n, m = S.m, WTP = S.WTP, W = I.W;
         TT *tabs = reinterpret_cast<TT *>(tab_raw);
-        TT *gs = tabs + n * m * WTP;
-        TT *cs = gs + 4 * m * WTP;
+        constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
+        TT *gs = tabs + n * m * WTP;          // e^b[p] rows
+        TT *cs = gs + NE * m * WTP;
         const int w0 = it.tile * WT;
         const int nm = n * m;
+        const bool runs = (WT == 64) && it.order >= 1 && it.order <= 4;
         // ---- stage the excitation records and the walker tile's tables ----
-        {
+        if (!runs) {
             // records as 4 x 32-bit words (global loads)
             const auto exg = MDE_G(uint32_t, S.ex) + (size_t)it.u0 * 4;
             uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
             for (int idx = tid; idx < (it.u1 - it.u0) * 4; idx += nthr) exw[idx] = exg[idx];
         }
-        // proposal tables are stored walker-tiled ([tile][e][WT]): a straight
-        // copy into the padded LDS rows, no index division
+        // tables are stored walker-tiled ([tile][e][WT]): straight copies into
+        // the padded LDS rows, no index division
         if (MODE == DM_PROPOSE) {
-            const size_t tn = (size_t)it.tile * nm * WT, tg = (size_t)it.tile * 4 * m * WT,
+            const size_t tn = (size_t)it.tile * nm * WT, tg = (size_t)it.tile * NE * m * WT,
                          tc = (size_t)it.tile * n * WT;
             if (sizeof(TT) == 8) {
-                const auto Tg = MDE_G(double, I.Tp) + tn;
-                const auto gg = MDE_G(double, I.g) + tg;
-                const auto cg = MDE_G(double, I.cp) + tc;
+                const auto Tg = MDE_G(double, S.T) + tn;
+                const auto gg = MDE_G(double, I.ev) + tg;
+                const auto cg = MDE_G(double, I.cc) + tc;
                 for (int idx = tid; idx < nm * WT; idx += nthr)
                     tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
-                for (int idx = tid; idx < 4 * m * WT; idx += nthr)
+                for (int idx = tid; idx < NE * m * WT; idx += nthr)
                     gs[(idx / WT) * WTP + idx % WT] = (TT)gg[idx];
                 for (int idx = tid; idx < n * WT; idx += nthr)
                     cs[(idx / WT) * WTP + idx % WT] = (TT)cg[idx];
             } else {
                 const auto Tg = MDE_G(float, I.Tp32) + tn;
-                const auto gg = MDE_G(float, I.g32) + tg;
-                const auto cg = MDE_G(float, I.cp32) + tc;
+                const auto gg = MDE_G(float, I.ev32) + tg;
+                const auto cg = MDE_G(float, I.cc32) + tc;
                 for (int idx = tid; idx < nm * WT; idx += nthr)
                     tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
-                for (int idx = tid; idx < 4 * m * WT; idx += nthr)
+                for (int idx = tid; idx < NE * m * WT; idx += nthr)
                     gs[(idx / WT) * WTP + idx % WT] = (TT)gg[idx];
                 for (int idx = tid; idx < n * WT; idx += nthr)
                     cs[(idx / WT) * WTP + idx % WT] = (TT)cg[idx];
@@ -220,21 +365,27 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
             }
         }
         __syncthreads();
-        double rhoA[4] = {0, 0, 0, 0};
-        double acc[NSUM] = {0, 0, 0, 0, 0};
-        if (MODE == DM_PROPOSE) {
-            const int w = w0 + wl;
-            if (w < W) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a) rhoA[a] = MDE_G(double, I.rhoA)[(size_t)w * 4 + a];
+        double acc[NSUM] = {0, 0, 0, 0, 0, 0};
+        if (runs) {
+            // wave `slot` takes a contiguous share of the item's excitations
+            const int len = it.u1 - it.u0;
+            const int ws = __builtin_amdgcn_readfirstlane(slot);
+            const int j0 = it.u0 + (int)(((long long)ws * len) / nslot);
+            const int j1 = it.u0 + (int)(((long long)(ws + 1) * len) / nslot);
+            switch (it.order) {
+                case 1: det_runs64<1, TT, MODE>(S, it.tile, j0, j1, tabs, gs, cs, wl, acc); break;
+                case 2: det_runs64<2, TT, MODE>(S, it.tile, j0, j1, tabs, gs, cs, wl, acc); break;
+                case 3: det_runs64<3, TT, MODE>(S, it.tile, j0, j1, tabs, gs, cs, wl, acc); break;
+                default: det_runs64<4, TT, MODE>(S, it.tile, j0, j1, tabs, gs, cs, wl, acc); break;
             }
-        }
-        switch (it.order) {
-            case 1: det_loop<1, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
-            case 2: det_loop<2, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
-            case 3: det_loop<3, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
-            case 4: det_loop<4, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
-            default: det_loop<0, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, rhoA, acc); break;
+        } else {
+            switch (it.order) {
+                case 1: det_loop<1, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+                case 2: det_loop<2, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+                case 3: det_loop<3, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+                case 4: det_loop<4, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+                default: det_loop<0, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+            }
         }
         __syncthreads();   // tables no longer needed: reuse LDS for the reduction
         if (MODE == DM_PROPOSE) {
@@ -525,9 +676,14 @@ hipError_t launch_nsum(hipStream_t st, const InstDev *d_inst, const InstDev &h,
 }
 
 // ---------------------------------------------------------------------------
-// finish: per walker, sum the partials of its tile in slot order and form
-// ratio = rho N'/N, grad = G^{x,y,z}/N', lap = G^L/N' (Sec. III ratio eq.,
-// Sec. IV eq. gradMDS); the reference excitation contributes C_0 (1, rho^a).
+// finish: per walker, sum the partials of its tile in slot order (the
+// reference excitation adds C_0 to N) and form the ratio (Sec. III ratio
+// eq.) and the derivatives (Sec. IV derivative eqs.).  FP64 form, with
+// rho N' = rho N - Q:
+//   ratio = rho N' / N,   grad^a = (kappa^a N + W^a) / (rho N'),
+// Q and W^a the q- and w^a-sums.  Mixed forms, with N' the sum over the
+// updated table and G^a the g^a-sums:
+//   ratio = rho N' / N_old,   grad^a = ((kappa^a / rho) N' + G^a) / N'.
 // ---------------------------------------------------------------------------
 
 __global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves,
@@ -540,33 +696,44 @@ __global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__re
     const SpinDev &S = I.s[mv.spin];
     const int WT = S.WT, t = w / WT, wl = w - t * WT;
     const double C0 = MDE_G(double, S.C)[(size_t)t * S.U * WT + wl];
-    double sum[NSUM];
-    sum[0] = C0;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) sum[1 + a] = C0 * MDE_G(double, I.rhoA)[(size_t)w * 4 + a];
+    double sum[NSUM] = {C0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
     const auto part = MDE_G(double, S.partial);
     for (int s = s0; s < s1; ++s) {
 #pragma unroll
         for (int q = 0; q < NSUM; ++q) sum[q] += part[((size_t)s * WT + wl) * NSUM + q];
     }
-    const double Np = sum[0];
     const double rho = I.rho[w];
-    const double ratio = rho * Np / I.Nold[w];
-    const double inv = 1.0 / Np;
-    I.Nnew[w] = Np;
+    const auto kap = MDE_G(double, I.kap) + (size_t)w * 4;
+    double ratio, rNp, d[4];
+    if (I.prec == 0) {
+        const double N = sum[0];
+        rNp = fma(rho, N, -sum[1]);       // rho N'
+        ratio = rNp / N;
+        const double inv = 1.0 / rNp;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) d[a] = fma(kap[a], N, sum[2 + a]) * inv;
+        I.Nnew[w] = rNp / rho;
+    } else {
+        const double Np = sum[0], ir = 1.0 / rho;
+        rNp = rho * Np;
+        ratio = rNp / I.Nold[w];
+        const double inv = 1.0 / Np;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) d[a] = fma(kap[a] * ir, Np, sum[1 + a]) * inv;
+        I.Nnew[w] = Np;
+    }
     int bits = I.st[w] & 2;
-    if (!(Np != 0.0) || !isfinite(Np)) bits |= 8;
-    const double g0 = sum[1] * inv, g1 = sum[2] * inv, g2 = sum[3] * inv, lp = sum[4] * inv;
-    if (!isfinite(ratio) || !isfinite(g0) || !isfinite(g1) || !isfinite(g2) || !isfinite(lp))
+    if (!(rNp != 0.0) || !isfinite(rNp)) bits |= 8;
+    if (!isfinite(ratio) || !isfinite(d[0]) || !isfinite(d[1]) || !isfinite(d[2]) || !isfinite(d[3]))
         bits |= 4;
     if (mv.ratio) mv.ratio[w] = ratio;
     if (mv.grad) {
-        mv.grad[(size_t)w * 3 + 0] = g0;
-        mv.grad[(size_t)w * 3 + 1] = g1;
-        mv.grad[(size_t)w * 3 + 2] = g2;
+        mv.grad[(size_t)w * 3 + 0] = d[0];
+        mv.grad[(size_t)w * 3 + 1] = d[1];
+        mv.grad[(size_t)w * 3 + 2] = d[2];
     }
-    if (mv.lap) mv.lap[w] = lp;
+    if (mv.lap) mv.lap[w] = d[3];
     if (mv.status && bits) mv.status[w] |= bits;
 }
 

@@ -184,146 +184,165 @@ hipError_t launch_table_gemm(hipStream_t st, const InstDev *d_inst, const InstDe
 }
 
 // ---------------------------------------------------------------------------
-// proposal, FP64: one block per walker tile, walker index fastest.
-//   c = A^-1 e_i, rho = a'.c (= det A'/det A), c' = c/rho,
-//   q = a'^T T_V - phi'_V,   T'_V = T_V - c' q^T   (Sec. III SM eqs., row form),
-//   rho^a = d^a_O . c',  g^a = d^a_V - d^a_O^T T'_V = d^a_V - d^a_O^T T_V + rho^a q
-// T'_V, g^a and c' are written walker-tiled, the layout the determinant
-// kernel stages into LDS.
+// proposal.  Common part: c = A^-1 e_i, rho = a'.c (= det A'/det A),
+// kappa^a = d^a_O . c,  q = a'^T T_V - phi'_V,  w^a = d^a_V - d^a_O^T T_V.
+//
+// FP64 form, in the frame of the current table T: for an excitation with
+// holes h and particles p let S = T[h][p] and y = adj(S) c[h].  The updated
+// table of Sec. III is T' = T - c q^T / rho; the matrix determinant lemma
+// and the bordered form of the row-replaced reference (Sec. IV-A) give
+//   rho R'_u   = rho det S - q[p] . y
+//   rho G^a_u  = kappa^a det S + w^a[p] . y
+// (R'_u = det S'_u, G^a_u = grad^a of the excited determinant over D_0(R')).
+// Every quantity is a polynomial in table entries: nothing is divided by rho
+// before the final per-walker quotients, so a move that lands near the
+// reference determinant's node keeps full accuracy.  T' is formed only on
+// acceptance.
+//
+// Mixed forms, in the frame of the updated table (Algorithm 1 as written):
+// T'_V = T_V - c' q^T with c' = c/rho is formed in FP64 from the FP32 table
+// and stored in FP32, with g^a = d^a_V - d^a_O^T T'_V = w^a + (kappa^a/rho) q;
+// then R'_u = det S'_u and G^a_u = (kappa^a/rho) R'_u + g^a[p] . adj(S') c'[h].
+// (With FP32 table entries the current-table frame would lose accuracy on
+// moves whose ratio is much smaller than rho: rho det S and q . y then
+// cancel.)
+//
+// One block per (walker tile, part): the tile's new orbital rows (occupied
+// part and the part's slice of virtuals) are copied into LDS with coalesced
+// loads; lanes are walkers.  Part 0 also writes the per-walker scalars and
+// the commit's row a'^T A^-1 - e_i^T.
 // ---------------------------------------------------------------------------
 
-// TT = double: FP64 tables.  TT = float (MIXED): FP32 table storage, every
-// product and the rank-one update in FP64, results rounded once to FP32.
-// Blocks: (walker tile, part) x instance; part `part` of `split` handles a
-// slice of the virtual orbitals; part 0 also writes the per-walker scalars.
+__host__ __device__ inline int odd_stride(int x) { return x | 1; }
+
 template <int WT, typename TT>
-__global__ void __launch_bounds__(1024)
-k_propose64(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1,
-            int split) {
+__global__ void __launch_bounds__(256)
+k_propose(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1,
+          int split) {
+    constexpr bool F64 = sizeof(TT) == 8;
     const int inst = blockIdx.y;
     const InstDev &I = insts[inst];
     const MoveArgs mv = moves ? moves[inst] : m1;
     const SpinDev &S = I.s[mv.spin];
     const int t = blockIdx.x / split, part = blockIdx.x % split;
     if (t >= S.n_tiles) return;
-    const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nm = n * m;
+    const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nn = n * n;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int w0 = t * WT, nw = min(WT, W - w0);
+    const int mc = (m + split - 1) / split, p0 = min(m, part * mc), p1 = min(m, p0 + mc);
+    const int ns = n + (p1 - p0);              // staged orbitals per component
+    const int ost = odd_stride(5 * ns);
     extern __shared__ double shp[];
-    double *c_s = shp;                 // [n][WT]
-    double *a_s = c_s + n * WT;        // [n][WT]
-    double *d_s = a_s + n * WT;        // [4][n][WT]
-    double *ir_s = d_s + 4 * n * WT;   // [WT] 1/rho
-    double *rA_s = ir_s + WT;          // [4][WT]
-    const auto B = MDE_G(double, S.B);
-    const auto orb = MDE_G(double, mv.new_orb);
+    double *o_s = shp;                         // [WT][ost]: 5 x (occupied, slice)
+    double *c_s = o_s + WT * ost;              // [n][WT]: c = A^-1 e_i
+    double *r_s = c_s + n * WT;                // [5][WT]: 1/rho, kappa^a / rho (mixed)
+    const auto orb = MDE_G(double, mv.new_orb) + (size_t)w0 * 5 * no;
+    for (int idx = tid; idx < nw * 5 * ns; idx += nthr) {
+        const int l = idx / (5 * ns), r = idx - l * 5 * ns, a = r / ns, j = r - a * ns;
+        const int p = j < n ? j : p0 + j;      // orbital index (virtual p0.. at n + p0)
+        o_s[l * ost + r] = orb[(size_t)l * 5 * no + a * no + p];
+    }
+    const auto Bg = MDE_G(double, S.B) + (size_t)w0 * nn;
     for (int idx = tid; idx < n * WT; idx += nthr) {
-        const int r = idx / WT, l = idx % WT, w = t * WT + l;
-        double c = 0.0, a = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-        if (w < W) {
-            const auto nr = orb + (size_t)w * 5 * no;
-            c = B[((size_t)w * n + r) * n + row];
-            a = nr[r];
-            d0 = nr[no + r];
-            d1 = nr[2 * no + r];
-            d2 = nr[3 * no + r];
-            d3 = nr[4 * no + r];
-        }
-        c_s[idx] = c;
-        a_s[idx] = a;
-        d_s[idx] = d0;
-        d_s[n * WT + idx] = d1;
-        d_s[2 * n * WT + idx] = d2;
-        d_s[3 * n * WT + idx] = d3;
+        const int r = idx / WT, l = idx % WT;
+        c_s[idx] = (l < nw) ? Bg[(size_t)l * nn + r * n + row] : 0.0;
     }
     __syncthreads();
+    if (part == 0 || !F64) {
+        for (int l = tid; l < WT; l += nthr) {
+            const int w = w0 + l;
+            double rho = 1.0, k[4] = {0.0, 0.0, 0.0, 0.0};
+            if (l < nw) {
+                const double *ol = o_s + l * ost;
+                rho = 0.0;
+                for (int r = 0; r < n; ++r) {
+                    const double c = c_s[r * WT + l];
+                    rho = fma(ol[r], c, rho);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) k[a] = fma(ol[(1 + a) * ns + r], c, k[a]);
+                }
+            }
+            if (!F64) {
+                const double ir = 1.0 / rho;
+                r_s[l] = ir;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) r_s[(1 + a) * WT + l] = k[a] * ir;
+            }
+            if (part == 0 && l < nw) {
+                I.rho[w] = rho;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) I.kap[(size_t)w * 4 + a] = k[a];
+                const int bits = (!isfinite(rho) || fabs(rho) < 1e-300) ? 2 : 0;
+                I.st[w] = (I.st[w] & ~2) | bits;
+            }
+        }
+    }
+    if (!F64) __syncthreads();
     if (part == 0) {
-        // row of the commit's rank-one update: a'^T A^-1 - e_i^T
-        const auto rr = MDE_GW(double, I.rrow) + (size_t)t * n * WT;
+        const auto cct = MDE_GW(double, I.cc) + (size_t)t * n * WT;
+        const auto rrt = MDE_GW(double, I.rrow) + (size_t)t * n * WT;
         for (int idx = tid; idx < n * WT; idx += nthr) {
-            const int j = idx / WT, l = idx % WT, w = t * WT + l;
+            const int j = idx / WT, l = idx % WT;
             double r = 0.0;
-            if (w < W) {
-                const auto Bw = B + (size_t)w * n * n;
-                for (int k = 0; k < n; ++k) r = fma(a_s[k * WT + l], Bw[(size_t)k * n + j], r);
+            if (l < nw) {
+                const double *ol = o_s + l * ost;
+                for (int k = 0; k < n; ++k) r = fma(ol[k], Bg[(size_t)l * nn + k * n + j], r);
                 r -= (j == row) ? 1.0 : 0.0;
             }
-            rr[idx] = r;
+            cct[idx] = c_s[idx];
+            if (!F64) I.cc32[(size_t)t * n * WT + idx] = (float)(c_s[idx] * r_s[l]);
+            rrt[idx] = r;
+        }
+        for (int idx = tid; idx < nw * no; idx += nthr) {
+            const int l = idx / no, p = idx - l * no;
+            I.newrow[(size_t)(w0 + l) * I.nomax + p] = orb[(size_t)l * 5 * no + p];
         }
     }
-    if (tid < WT) {
-        const int l = tid, w = t * WT + l;
-        double rho = 0.0, dc[4] = {0, 0, 0, 0};
-        for (int r = 0; r < n; ++r) {
-            const double c = c_s[r * WT + l];
-            rho = fma(a_s[r * WT + l], c, rho);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) dc[a] = fma(d_s[(a * n + r) * WT + l], c, dc[a]);
-        }
-        const double irho = (w < W) ? 1.0 / rho : 0.0;
-        ir_s[l] = irho;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) rA_s[a * WT + l] = dc[a] * irho;
-        if (w < W && part == 0) {
-            I.rho[w] = rho;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) I.rhoA[(size_t)w * 4 + a] = dc[a] * irho;
-            const int bits = (!isfinite(rho) || fabs(rho) < 1e-300) ? 2 : 0;
-            I.st[w] = (I.st[w] & ~2) | bits;
-        }
-    }
-    __syncthreads();
-    const bool f64 = sizeof(TT) == 8;
-    const auto Tt = MDE_G(TT, f64 ? (const void *)S.T : (const void *)S.T32) + (size_t)t * nm * WT;
-    const auto Tpt = MDE_GW(TT, f64 ? (void *)I.Tp : (void *)I.Tp32) + (size_t)t * nm * WT;
-    const auto gt = MDE_GW(TT, f64 ? (void *)I.g : (void *)I.g32) + (size_t)t * 4 * m * WT;
-    // c' in FP64 for the commit's update of A^-1, and in the table type for
-    // the determinant kernel
-    const auto cpd = MDE_GW(double, I.cp) + (size_t)t * n * WT;
-    const auto cpt = MDE_GW(TT, f64 ? (void *)I.cp : (void *)I.cp32) + (size_t)t * n * WT;
-    if (part == 0) {
-        for (int idx = tid; idx < n * WT; idx += nthr) {
-            const double v = c_s[idx] * ir_s[idx % WT];
-            cpd[idx] = v;
-            if (!f64) cpt[idx] = (TT)v;
-        }
-    }
-    const int mc = (m + split - 1) / split, p0 = part * mc, p1 = min(m, p0 + mc);
+    // the part's slice of virtuals
+    const auto Tt = MDE_G(TT, F64 ? (const void *)S.T : (const void *)S.T32) + (size_t)t * n * m * WT;
+    constexpr int NE = F64 ? 5 : 4;
+    const auto evt = MDE_GW(TT, F64 ? (void *)I.ev : (void *)I.ev32) + (size_t)t * NE * m * WT;
     for (int idx = p0 * WT + tid; idx < p1 * WT; idx += nthr) {
-        const int p = idx / WT, l = idx % WT, w = t * WT + l;
-        double v = 0.0, wa[4] = {0, 0, 0, 0};
-        for (int r = 0; r < n; ++r) {
-            const double tv = (double)Tt[(size_t)(r * m + p) * WT + l];
-            v = fma(a_s[r * WT + l], tv, v);
+        const int p = idx / WT, l = idx % WT, jp = n + p - p0;
+        double q = 0.0, wa[4] = {0.0, 0.0, 0.0, 0.0};
+        if (l < nw) {
+            const double *ol = o_s + l * ost;
+            double v = 0.0, da[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int r = 0; r < n; ++r) {
+                const double tv = (double)Tt[(size_t)(r * m + p) * WT + l];
+                v = fma(ol[r], tv, v);
 #pragma unroll
-            for (int a = 0; a < 4; ++a) wa[a] = fma(d_s[(a * n + r) * WT + l], tv, wa[a]);
-        }
-        double q = 0.0;
-        double dv[4] = {0, 0, 0, 0};
-        if (w < W) {
-            const auto nr = orb + (size_t)w * 5 * no + n + p;
-            q = v - nr[0];
+                for (int a = 0; a < 4; ++a) da[a] = fma(ol[(1 + a) * ns + r], tv, da[a]);
+            }
+            q = v - ol[jp];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) dv[a] = nr[(1 + a) * no];
+            for (int a = 0; a < 4; ++a) wa[a] = ol[(1 + a) * ns + jp] - da[a];
         }
+        if (F64) {
+            evt[(size_t)(p * 5) * WT + l] = (TT)q;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-            gt[(size_t)(a * m + p) * WT + l] = (TT)((w < W) ? dv[a] - wa[a] + rA_s[a * WT + l] * q : 0.0);
-        const double qi = q * ir_s[l];
-        for (int r = 0; r < n; ++r) {
-            const size_t o = (size_t)(r * m + p) * WT + l;
-            Tpt[o] = (TT)fma(-c_s[r * WT + l], qi, (double)Tt[o]);
+            for (int a = 0; a < 4; ++a) evt[(size_t)(p * 5 + 1 + a) * WT + l] = (TT)wa[a];
+        } else {
+            const double ir = r_s[l], qi = q * ir;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                evt[(size_t)(p * 4 + a) * WT + l] = (TT)fma(r_s[(1 + a) * WT + l], q, wa[a]);
+            const auto Tpt = MDE_GW(float, I.Tp32) + (size_t)t * n * m * WT;
+            for (int r = 0; r < n; ++r) {
+                const size_t o = (size_t)(r * m + p) * WT + l;
+                Tpt[o] = (float)fma(-c_s[r * WT + l], qi, (double)Tt[o]);
+            }
         }
-    }
-    const int nc = (no + split - 1) / split, q0 = part * nc, q1 = min(no, q0 + nc);
-    for (int idx = q0 * WT + tid; idx < q1 * WT; idx += nthr) {
-        const int p = idx / WT, l = idx % WT, w = t * WT + l;
-        if (w < W) I.newrow[(size_t)w * I.nomax + p] = orb[(size_t)w * 5 * no + p];
     }
 }
 
-// ---------------------------------------------------------------------------
-// proposal, MIXED (Algorithm 1 as written: update the inverse, then rebuild
-// the table with one GEMM).  FP64 part, one wave per walker:
+static size_t propose_lds(int nmax, int mmax, int WT, int split) {
+    const int mc = (mmax + split - 1) / split;
+    return sizeof(double) * (size_t)WT * (odd_stride(5 * (nmax + mc)) + nmax + 5);
+}
+
+// proposal, MIXED_GEMM (Algorithm 1 as written: update the inverse, then
+// rebuild the table with one GEMM).  FP64 part, one wave per walker:
 //   c = A^-1 e_i, rho = a'.c, c' = c/rho, r = a'^T A^-1,
 //   A'^-1 = A^-1 - c' (r - e_i^T)                  -> FP32 operand rows 0..n-1
 //   e^a = d^a_O^T A'^-1 = d^a_O^T A^-1 - rho^a (r - e_i^T)  -> rows n..n+3
@@ -360,13 +379,13 @@ k_propose_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ 
     if (lane < n) {
         const int WT = S.WT;
         const size_t o = ((size_t)(w / WT) * n + lane) * WT + (w % WT);
-        I.cp[o] = c * irho;
-        I.cp32[o] = (float)(c * irho);
+        I.cc[o] = c;
+        I.cc32[o] = (float)(c * irho);
     }
     if (lane == 0) {
         I.rho[w] = rho;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) I.rhoA[(size_t)w * 4 + a] = rhoA[a];
+        for (int a = 0; a < 4; ++a) I.kap[(size_t)w * 4 + a] = dc[a];
         int bits = 0;
         if (!isfinite(rho) || fabs(rho) < 1e-300) bits |= 2;
         I.st[w] = (I.st[w] & ~2) | bits;
@@ -433,7 +452,7 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
     const int lr = lane & 15, lk = lane >> 4;
     const int WT = S.WT, tw = w / WT, lw = w % WT;
     float *__restrict__ Tp = I.Tp32 + (size_t)tw * n * m * WT + lw;
-    float *__restrict__ g32 = I.g32 + (size_t)tw * 4 * m * WT + lw;
+    float *__restrict__ g32 = I.ev32 + (size_t)tw * 4 * m * WT + lw;
     for (int t = wave; t < RT * CT; t += 4) {
         const int rt = t / CT, ct = t - rt * CT;
         // each MFMA multiplies FP32 operands over a K-block of 4 with FP32
@@ -455,7 +474,7 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
             if (r < n) Tp[(size_t)(r * m + p) * WT] = (float)acc64[i];
             else if (r < rows) {
                 const int a = r - n;
-                g32[(size_t)(a * m + p) * WT] = (float)(nr[(1 + a) * no + n + p] - acc64[i]);
+                g32[(size_t)(p * 4 + a) * WT] = (float)(nr[(1 + a) * no + n + p] - acc64[i]);
             }
         }
     }
@@ -464,44 +483,59 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
 hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                           const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
                           int mmax, int WT, int max_tiles, int split) {
-    if (prec == 0 || prec == 1) {
-        const int threads = (WT >= 16 && split == 1) ? 1024 : 256;
-        const size_t lds = sizeof(double) * ((size_t)6 * nmax * WT + 5 * WT);
-        dim3 g(max_tiles * split, n_inst);
-#define MDE_PP(X)                                                                                \
-    case X:                                                                                      \
-        if (prec == 0) {                                                                         \
-            hipLaunchKernelGGL((k_propose64<X, double>), g, dim3(threads), lds, st, d_insts,    \
-                               d_moves, m1, split);                                              \
-        } else {                                                                                 \
-            hipLaunchKernelGGL((k_propose64<X, float>), g, dim3(threads), lds, st, d_insts,     \
-                               d_moves, m1, split);                                              \
-        }                                                                                        \
-        break;
-        switch (WT) {
-            MDE_PP(1) MDE_PP(2) MDE_PP(4) MDE_PP(8) MDE_PP(16) MDE_PP(32) MDE_PP(64)
-            default: return hipErrorInvalidValue;
-        }
-#undef MDE_PP
+    if (prec == 2) {
+        dim3 grid((maxW + 3) / 4, n_inst);
+        hipLaunchKernelGGL(k_propose_mixed, grid, dim3(256), 0, st, d_insts, d_moves, m1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int rp = (nmax + 4 + 15) & ~15, kp = (nmax + 3) & ~3, mp = (mmax + 15) & ~15;
+        const size_t lds = sizeof(float) * ((size_t)rp * (kp + 1) + (size_t)kp * mp);
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_gemm_mixed,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_gemm_mixed, dim3(maxW, n_inst), dim3(256), lds, st, d_insts, d_moves,
+                           m1);
         return hipGetLastError();
     }
-    dim3 grid((maxW + 3) / 4, n_inst);
-    hipLaunchKernelGGL(k_propose_mixed, grid, dim3(256), 0, st, d_insts, d_moves, m1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int rp = (nmax + 4 + 15) & ~15, kp = (nmax + 3) & ~3, mp = (mmax + 15) & ~15;
-    const size_t lds = sizeof(float) * ((size_t)rp * (kp + 1) + (size_t)kp * mp);
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_gemm_mixed,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_gemm_mixed, dim3(maxW, n_inst), dim3(256), lds, st, d_insts, d_moves, m1);
+    const size_t lds = propose_lds(nmax, mmax, WT, split);
+    dim3 g(max_tiles * split, n_inst);
+#define MDE_PP(X)                                                                              \
+    case X:                                                                                    \
+        if (prec == 0) {                                                                       \
+            if (lds > 65536)                                                                   \
+                (void)hipFuncSetAttribute((const void *)k_propose<X, double>,                  \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+            hipLaunchKernelGGL((k_propose<X, double>), g, dim3(256), lds, st, d_insts, d_moves, \
+                               m1, split);                                                     \
+        } else {                                                                               \
+            if (lds > 65536)                                                                   \
+                (void)hipFuncSetAttribute((const void *)k_propose<X, float>,                   \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+            hipLaunchKernelGGL((k_propose<X, float>), g, dim3(256), lds, st, d_insts, d_moves, \
+                               m1, split);                                                     \
+        }                                                                                      \
+        break;
+    switch (WT) {
+        MDE_PP(1) MDE_PP(2) MDE_PP(4) MDE_PP(8) MDE_PP(16) MDE_PP(32) MDE_PP(64)
+        default: return hipErrorInvalidValue;
+    }
+#undef MDE_PP
     return hipGetLastError();
 }
 
+int propose_split_limit(int nmax, int mmax, int WT, size_t lds_max) {
+    // smallest split whose LDS footprint fits
+    for (int s = 1; s <= mmax; ++s)
+        if (propose_lds(nmax, mmax, WT, s) <= lds_max) return s;
+    return 0;
+}
+
 // ---------------------------------------------------------------------------
-// commit (Sec. III SM eq., row form): for accepted walkers
-//   A^-1 <- A^-1 - c' (a'^T A^-1 - e_i^T),  T_V <- T'_V,  Phi row i <- new,
-//   log|det A| += log|rho|, N <- N'.  One block per walker tile.
+// commit (Sec. III SM eq., row form): for accepted walkers, with c' = c/rho,
+//   A^-1 <- A^-1 - c' (a'^T A^-1 - e_i^T),   Phi row i <- new,
+//   T_V  <- T'_V = A'^-1 Phi'_V  (FP64: formed here as T_V - c' q^T; mixed
+//                                 forms: the proposal's FP32 table),
+//   log|det A| += log|rho|,  N <- N'.
 // ---------------------------------------------------------------------------
 
 template <int WT>
@@ -517,28 +551,37 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
     const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nm = n * m;
     const int tid = threadIdx.x, nthr = blockDim.x;
     __shared__ int acc_s[64];
+    __shared__ double ir_s[64];
     if (tid < WT) {
         const int w = t * WT + tid;
-        acc_s[tid] = (w < W) ? (int)mv.accept[w] : 0;
+        const int a = (w < W) ? (int)mv.accept[w] : 0;
+        acc_s[tid] = a;
+        ir_s[tid] = a ? 1.0 / I.rho[w] : 0.0;
     }
     __syncthreads();
     const auto nrow = MDE_G(double, I.newrow);
     const auto rr = MDE_G(double, I.rrow) + (size_t)t * n * WT;
-    const auto cp = MDE_G(double, I.cp) + (size_t)t * n * WT;
-    // A^-1 rows of this part (the update row a'^T A^-1 - e_i^T was formed
-    // from the pre-update inverse by the proposal)
+    const auto cc = MDE_G(double, I.cc) + (size_t)t * n * WT;
+    // A^-1 rows of this part (the update row was formed from the pre-update
+    // inverse by the proposal)
     const int rc = (n + split - 1) / split, r0 = part * rc, r1 = min(n, r0 + rc);
     for (int idx = r0 * n * WT + tid; idx < r1 * n * WT; idx += nthr) {
         const int l = idx % WT, rj = idx / WT, r = rj / n, j = rj - r * n;
         if (!acc_s[l]) continue;
         const size_t o = ((size_t)(t * WT + l) * n + r) * n + j;
-        S.B[o] = fma(-cp[r * WT + l], rr[j * WT + l], S.B[o]);
+        S.B[o] = fma(-cc[r * WT + l] * ir_s[l], rr[j * WT + l], S.B[o]);
     }
     const size_t tb = (size_t)t * nm * WT;
     const int ec = (nm * WT + split - 1) / split, e0 = part * ec, e1 = min(nm * WT, e0 + ec);
     if (I.prec == 0) {
-        for (int idx = e0 + tid; idx < e1; idx += nthr)
-            if (acc_s[idx % WT]) S.T[tb + idx] = I.Tp[tb + idx];
+        const auto qv = MDE_G(double, I.ev) + (size_t)t * 5 * m * WT;
+        for (int idx = e0 + tid; idx < e1; idx += nthr) {
+            const int l = idx % WT;
+            if (!acc_s[l]) continue;
+            const int e = idx / WT, r = e / m, p = e - r * m;
+            const double cr = cc[r * WT + l] * ir_s[l], qp = qv[(size_t)p * 5 * WT + l];
+            S.T[tb + idx] = fma(-cr, qp, S.T[tb + idx]);
+        }
     } else {
         for (int idx = e0 + tid; idx < e1; idx += nthr)
             if (acc_s[idx % WT]) S.T32[tb + idx] = I.Tp32[tb + idx];
@@ -563,7 +606,6 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
 hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
                          int mmax, int WT, int max_tiles, int split) {
-    (void)prec; (void)mmax; (void)maxW; (void)nmax;
     dim3 g(max_tiles * split, n_inst);
 #define MDE_AC(X)                                                                              \
     case X:                                                                                    \
@@ -574,6 +616,7 @@ hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int
         default: return hipErrorInvalidValue;
     }
 #undef MDE_AC
+    (void)prec; (void)maxW; (void)nmax; (void)mmax;
     return hipGetLastError();
 }
 

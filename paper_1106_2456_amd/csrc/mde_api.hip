@@ -197,7 +197,7 @@ static size_t det_lds(const SpinHost &s, int WT, int threads, int prec, bool pro
     const int WTP = (WT >= 8) ? WT + 1 : WT;
     const size_t esz = prec == 0 ? 8 : 4;
     size_t tab = (size_t)s.n * s.m * WTP * esz;
-    if (propose) tab += (size_t)(4 * s.m + s.n) * WTP * esz;
+    if (propose) tab += (size_t)((prec == 0 ? 5 : 4) * s.m + s.n) * WTP * esz;
     const size_t red = propose ? (size_t)(threads / 64) * WT * NSUM * 8 : 0;
     return (size_t)ex_cap * 16 + std::max(tab, red);
 }
@@ -268,13 +268,13 @@ static int item_size_for(const mde_ctx *c, const SpinHost &sp, int W, int WT, in
 static Plan default_plan(const mde_ctx *c, int W) {
     Plan p{};
     const size_t esz = c->d.precision == 0 ? 8 : 4;
-    // largest walker tile whose tables fit in ~96 KB of LDS for both spins
+    // largest walker tile whose tables fit in ~112 KB of LDS for both spins
     int WT = 64;
     for (int s = 0; s < 2; ++s) {
         const SpinHost &sp = c->sp[s];
-        const size_t per_w = (size_t)(sp.n * sp.m + 4 * sp.m + sp.n) * esz;
+        const size_t per_w = (size_t)(sp.n * sp.m + (esz == 8 ? 5 : 4) * sp.m + sp.n) * esz;
         int wt = 64;
-        while (wt > 1 && per_w * (wt + (wt >= 8 ? 1 : 0)) > 96 * 1024) wt /= 2;
+        while (wt > 1 && per_w * (wt + (wt >= 8 ? 1 : 0)) > 112 * 1024) wt /= 2;
         WT = std::min(WT, wt);
     }
     WT = std::min(WT, std::max(1, pow2_floor(std::max(W, 1))));
@@ -413,15 +413,14 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
     h.Nnew = cv.take<double>(W);
     h.rho = cv.take<double>(W);
     const size_t Wq = (size_t)W + 64;
-    h.cp = cv.take<double>(Wq * nmax);
-    h.Tp = prec == 0 ? cv.take<double>(Wq * nmax * mmax) : nullptr;
-    h.rhoA = cv.take<double>((size_t)W * 4);
+    h.cc = cv.take<double>(Wq * nmax);
+    h.kap = cv.take<double>((size_t)W * 4);
     h.rrow = cv.take<double>(Wq * nmax);
     h.npart = cv.take<double>(Wq * NSPLIT);
-    h.g = prec == 0 ? cv.take<double>(Wq * 4 * mmax) : nullptr;
+    h.ev = prec == 0 ? cv.take<double>(Wq * 5 * mmax) : nullptr;
     h.newrow = cv.take<double>((size_t)W * nomax);
-    h.g32 = prec != 0 ? cv.take<float>(Wq * 4 * mmax) : nullptr;
-    h.cp32 = prec != 0 ? cv.take<float>(Wq * nmax) : nullptr;
+    h.ev32 = prec != 0 ? cv.take<float>(Wq * 4 * mmax) : nullptr;
+    h.cc32 = prec != 0 ? cv.take<float>(Wq * nmax) : nullptr;
     h.Tp32 = prec != 0 ? cv.take<float>(Wq * nmax * mmax) : nullptr;
     h.Ap32 = prec == 2 ? cv.take<float>((size_t)W * (nmax + 4) * nmax) : nullptr;
     h.st = cv.take<int32_t>(W);
@@ -491,6 +490,14 @@ static int row_split(int n_cu, int blocks, int cap) {
     int s = (2 * n_cu + blocks - 1) / std::max(blocks, 1);
     s = std::min(s, std::min(std::max(cap, 1), 16));
     return std::max(s, 1);
+}
+
+// parts of the proposal grid: enough blocks to fill the chip, and enough
+// parts that one part's orbital slice fits in LDS
+static int prop_split(int n_cu, int blocks, int nmax, int mmax, int WT) {
+    const int lim = propose_split_limit(nmax, mmax, WT, 160 * 1024);
+    if (lim == 0) return 0;
+    return std::max(row_split(n_cu, blocks, mmax), lim);
 }
 
 static MoveArgs no_move() {
@@ -896,9 +903,10 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
     m.lap = lap;
     m.status = status;
     const int nmax = c->h.nmax, mmax = c->h.mmax;
+    const int split = prop_split(c->n_cu, c->h.s[s].n_tiles, nmax, mmax, c->WT);
+    if (split == 0) MDE_FAIL(c, MDE_UNSUPPORTED, "proposal does not fit in LDS");
     MDE_HIP(c, launch_propose(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, nmax, mmax,
-                              c->WT, c->h.s[s].n_tiles,
-                              row_split(c->n_cu, c->h.s[s].n_tiles, c->sp[s].m)));
+                              c->WT, c->h.s[s].n_tiles, split));
     SpinHost &sp = c->sp[s];
     const bool prof = c->prof_on && 2 * (c->prof_used + 1) <= (int)c->prof_ev.size();
     if (prof) MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream));
@@ -1437,8 +1445,10 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const
     if (st) return st;
     const MoveArgs none = no_move();
     const int gt = (g->maxW + g->WT - 1) / g->WT;
+    const int split = prop_split(g->ctx[0]->n_cu, gt * n, g->nmax, g->mmax, g->WT);
+    if (split == 0) MDE_GFAIL(g, MDE_UNSUPPORTED, "proposal does not fit in LDS");
     if (launch_propose(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, g->prec, g->nmax,
-                       g->mmax, g->WT, gt, row_split(g->ctx[0]->n_cu, gt * n, g->mmax)) != hipSuccess)
+                       g->mmax, g->WT, gt, split) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "propose launch");
     if (launch_det(g->stream, g->d_insts, n, g->d_items, g->n_items, g->ex_cap, g->d_moves, none,
                    DM_PROPOSE, g->prec, g->WT, g->lds, g->threads, g->grid, g->ctx[0]->h.counter,

@@ -9,7 +9,7 @@ namespace mde {
 constexpr int MAXN = 64;     // electrons per spin
 constexpr int MAXM = 256;    // virtual orbitals per spin
 constexpr int MAXK = 8;      // excitation order
-constexpr int NSUM = 5;      // N, and the x, y, z, laplacian numerators
+constexpr int NSUM = 6;      // sums over excitations: N, q-term, x, y, z, laplacian
 
 // One unit of determinant work: excitations [u0, u1) of order `order` of
 // spin `spin` for the walkers of tile `tile` of instance `inst`.  Results go
@@ -64,20 +64,19 @@ struct InstDev {
     double *Nnew;    // [W] proposed N'
     double *rho;     // [W] det A'/det A
     // proposal of the moving spin (n, m of that spin), walker-tiled:
-    double *cp;      // tiled [n]    c' = A'^-1 e_i
-    double *Tp;      // tiled [n*m]  T'_V (FP64 mode)
-    double *g;       // tiled [4*m]  g^a (FP64 mode)
-    double *rhoA;    // [W][4] rho^a
+    double *cc;      // tiled [n]    c = A^-1 e_i
+    double *kap;     // [W][4]       kappa^a = d^a_O . c
+    double *ev;      // tiled [m][5] FP64 form: (q, w^x, w^y, w^z, w^L) per particle
+    float *ev32;     // tiled [m][4] mixed forms: g^a of the updated table
+    float *cc32;     // tiled [n]    mixed forms: c' = c / rho
+    float *Tp32;     // tiled [n*m]  mixed forms: updated table T'_V
+    float *Ap32;     // [W][nmax+4][nmax] MIXED_GEMM operand: rows of A'^-1, then e^a
     double *rrow;    // tiled [n]    a'^T A^-1 - e_i^T (for the commit)
     double *npart;   // [NSPLIT][n_tiles*WT] partial N sums
     double *newrow;  // [W][nomax] proposed orbital values of the moved electron
-    float *g32;      // tiled [4*m] (mixed)
-    float *cp32;     // tiled [n] (mixed)
-    float *Tp32;     // tiled [n*m] proposed table (mixed)
-    float *Ap32;     // [W][nmax+4][nmax] rows of A'^-1 then e^a (mixed GEMM operand)
     int32_t *st;     // [W] internal status bits
     int32_t *counter;  // work-queue counter of the persistent kernel
-    double *Lnew;    // [W] scratch
+    double *Lnew;    // [W] adjoint scratch: go / N per walker
 };
 
 // Per-call move arguments (device array for groups, by value otherwise).
@@ -115,6 +114,8 @@ hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst,
                       const MoveArgs *d_moves, const MoveArgs &m1, int mode, int prec,
                       int WT, size_t lds_bytes, int threads, int grid, int32_t *counter,
                       const double *tab0, const double *tab1);
+// smallest part count of the proposal whose LDS footprint fits lds_max (0: none)
+int propose_split_limit(int nmax, int mmax, int WT, size_t lds_max);
 hipError_t launch_finish(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int32_t *counter);
 hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,

@@ -138,4 +138,54 @@ MDE_HD F small_det_generic(int k, const F col[8][8], const F c[8], F y[8]) {
     return det;
 }
 
+// Run form.  With the first K-1 columns P_0..P_{K-2} of S fixed, det S is
+// linear in the last column b: det [P_0 .. P_{K-2}, b] = u . b, u the
+// cofactors of the last column (1; a 2-d rotation; the cross product; the
+// 4-d cross product from the 2 x 2 minors of the first two columns).
+template <typename F>
+MDE_HD void cross4(const F x[4], const F y[4], const F z[4], F w[4]) {
+    const F m01 = x[0] * y[1] - x[1] * y[0], m02 = x[0] * y[2] - x[2] * y[0];
+    const F m03 = x[0] * y[3] - x[3] * y[0], m12 = x[1] * y[2] - x[2] * y[1];
+    const F m13 = x[1] * y[3] - x[3] * y[1], m23 = x[2] * y[3] - x[3] * y[2];
+    w[0] = -m12 * z[3] + m13 * z[2] - m23 * z[1];
+    w[1] = m02 * z[3] - m03 * z[2] + m23 * z[0];
+    w[2] = -m01 * z[3] + m03 * z[1] - m13 * z[0];
+    w[3] = m01 * z[2] - m02 * z[1] + m12 * z[0];
+}
+
+template <int K, typename F>
+MDE_HD void last_cofactors(const F P[(K > 1 ? K - 1 : 1)][K], F u[K]) {
+    if constexpr (K == 1) {
+        u[0] = F(1);
+    } else if constexpr (K == 2) {
+        u[0] = -P[0][1];
+        u[1] = P[0][0];
+    } else if constexpr (K == 3) {
+        u[0] = P[0][1] * P[1][2] - P[0][2] * P[1][1];
+        u[1] = P[0][2] * P[1][0] - P[0][0] * P[1][2];
+        u[2] = P[0][0] * P[1][1] - P[0][1] * P[1][0];
+    } else {
+        static_assert(K == 4, "run form is written for orders 1..4");
+        cross4<F>(P[0], P[1], P[2], u);
+    }
+}
+
+// y_j = det(S with column j replaced by c) for j < K-1 is v_j . b with v_j
+// the last-column cofactors of the prefix whose column j is c; y_{K-1} = u . c.
+template <int K, typename F>
+MDE_HD void prefix_cofactors(const F P[(K > 1 ? K - 1 : 1)][K], const F c[K], F u[K],
+                             F v[(K > 1 ? K - 1 : 1)][K], F &ylast) {
+    constexpr int KP = K - 1, KQ = K > 1 ? K - 1 : 1;
+    last_cofactors<K, F>(P, u);
+    for (int j = 0; j < KP; ++j) {
+        F Q[KQ][K];
+        for (int i = 0; i < KP; ++i)
+            for (int r = 0; r < K; ++r) Q[i][r] = (i == j) ? c[r] : P[i][r];
+        last_cofactors<K, F>(Q, v[j]);
+    }
+    F s = F(0);
+    for (int r = 0; r < K; ++r) s += u[r] * c[r];
+    ylast = s;
+}
+
 }  // namespace mde
