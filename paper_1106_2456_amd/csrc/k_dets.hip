@@ -133,7 +133,8 @@ __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
 // ---- walker tile 64: one excitation per wave, evaluated in runs ----------
 //
 // The lanes of a wave are 64 walkers and every index is wave-uniform: the
-// records are read through the scalar cache and all control flow is scalar.
+// records (staged in LDS with the tables) are broadcast to the wave and all
+// control flow is scalar.
 // Excitations are sorted by holes, then particles, so consecutive
 // excitations of one order share their holes h_0..h_{K-1} and, often, their
 // first K-1 particles (the prefix).  Within such a run only the last column
@@ -147,12 +148,13 @@ __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
 // on closing the run
 //   acc[0] += Nrun,  acc[1+b] += y_{K-1} Zrun^b + sum_j e^b[p_j] Yrun_j.
 
-#define MDE_K(T, p) ((const T __attribute__((address_space(4))) *)(p))
+
 
 __device__ __forceinline__ int byte_of(uint32_t w, int i) { return (int)((w >> (8 * i)) & 0xffu); }
 
 template <int K, typename TT, int MODE>
 __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, int j1,
+                                           const uint32_t *exw, int u0,
                                            const TT *__restrict__ tabs, const TT *__restrict__ gs,
                                            const TT *__restrict__ cs, int wl, double acc[NSUM]) {
     constexpr int KP = K - 1;                  // prefix length
@@ -161,8 +163,8 @@ __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, i
     constexpr int WTP = 65;
     constexpr int D = 4;                       // CI weights loaded ahead
     constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
+    if (j0 >= j1) return;
     const int m = S.m;
-    const auto exr = MDE_K(uint32_t, S.ex);   // words x (holes 0..3), z (particles 0..3)
     const size_t cb0 = (size_t)tile * S.U * 64 + wl;
     const auto Cg = MDE_G(double, S.C) + cb0;
     const auto Rg = MDE_GW(double, S.R) + cb0;
@@ -250,27 +252,171 @@ __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, i
         for (int b = 0; b < NE; ++b) Zrun[b] = fma(Cu, (double)gs[(q * NE + b) * WTP + wl], Zrun[b]);
     };
 
-    double cb[D];
+    // records and CI weights of the next group are loaded while the current
+    // group is evaluated; indices are clamped into the range so every load
+    // is unconditional (a fixed number of loads in flight).  Two register
+    // sets alternate, so no copy waits for a load in flight.
+    uint32_t hA[D], pA[D], hB[D], pB[D];
+    double cA[D], cB[D];
+    auto fetch = [&](int jb, uint32_t (&h)[D], uint32_t (&pp)[D], double (&cv)[D]) {
 #pragma unroll
-    for (int i = 0; i < D; ++i)
-        cb[i] = (MODE == DM_PROPOSE && j0 + i < j1) ? Cg[(size_t)(j0 + i) * 64] : 0.0;
-    for (int j = j0; j < j1; j += D) {
-        double cn[D];
+        for (int i = 0; i < D; ++i) {
+            const int jj = min(jb + i, j1 - 1);
+            h[i] = exw[4 * (jj - u0)];          // word x: holes 0..3
+            pp[i] = exw[4 * (jj - u0) + 2];     // word z: particles 0..3
+            cv[i] = MODE == DM_PROPOSE ? Cg[(size_t)jj * 64] : 0.0;
+        }
+        // keep the compiler from moving these loads next to their use one
+        // group later (an empty asm with a memory clobber emits nothing)
+        __asm__ volatile("" ::: "memory");
+    };
+    auto run_group = [&](int jb, const uint32_t (&h)[D], const uint32_t (&pp)[D],
+                         const double (&cv)[D]) {
 #pragma unroll
         for (int i = 0; i < D; ++i)
-            cn[i] = (MODE == DM_PROPOSE && j + D + i < j1) ? Cg[(size_t)(j + D + i) * 64] : 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-            if (j + i < j1) step(exr[4 * (j + i)], exr[4 * (j + i) + 2], cb[i], j + i);
-#pragma unroll
-        for (int i = 0; i < D; ++i) cb[i] = cn[i];
+            if (jb + i < j1)
+                step(__builtin_amdgcn_readfirstlane(h[i]), __builtin_amdgcn_readfirstlane(pp[i]), cv[i],
+                     jb + i);
+    };
+    fetch(j0, hA, pA, cA);
+    for (int j = j0; j < j1; j += 2 * D) {
+        fetch(j + D, hB, pB, cB);
+        run_group(j, hA, pA, cA);
+        if (j + D >= j1) break;
+        fetch(j + 2 * D, hA, pA, cA);
+        run_group(j + D, hB, pB, cB);
     }
     if (MODE == DM_PROPOSE && open) close_run();
 }
 
+// Orders whose prefix runs are short (triples and quadruples rarely share
+// their first K-1 particles): every excitation gathers its K x K block, c[h]
+// and e^b[p_j], in groups of D with no branches between them, so the LDS
+// reads of one excitation overlap the arithmetic of the previous one.  Past
+// the end of the range the group repeats the last excitation with weight 0
+// (and, for values, rewrites the same ratio).
+template <int K, typename TT, int MODE>
+__device__ __forceinline__ void det_direct64(const SpinDev &S, int tile, int j0, int j1,
+                                             const uint32_t *exw, int u0,
+                                             const TT *__restrict__ tabs, const TT *__restrict__ gs,
+                                             const TT *__restrict__ cs, int wl, double acc[NSUM]) {
+    constexpr int WTP = 65;
+    constexpr int D = 4;
+    constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
+    if (j0 >= j1) return;
+    const int m = S.m;
+    const size_t cb0 = (size_t)tile * S.U * 64 + wl;
+    const auto Cg = MDE_G(double, S.C) + cb0;
+    const auto Rg = MDE_GW(double, S.R) + cb0;
+    uint32_t hA[D], pA[D], hB[D], pB[D];
+    double cA[D], cB[D];
+    auto fetch = [&](int jb, uint32_t (&h)[D], uint32_t (&pp)[D], double (&cv)[D]) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int jj = min(jb + i, j1 - 1);
+            h[i] = exw[4 * (jj - u0)];          // word x: holes 0..3
+            pp[i] = exw[4 * (jj - u0) + 2];     // word z: particles 0..3
+            cv[i] = MODE == DM_PROPOSE ? Cg[(size_t)jj * 64] : 0.0;
+        }
+        __asm__ volatile("" ::: "memory");
+    };
+    auto run_group = [&](int j, const uint32_t (&hc)[D], const uint32_t (&pc)[D],
+                         const double (&cb)[D]) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            int h[K], hm[K], p[K];
+            const uint32_t hw = __builtin_amdgcn_readfirstlane(hc[i]);
+            const uint32_t pw = __builtin_amdgcn_readfirstlane(pc[i]);
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                h[r] = byte_of(hw, r);
+                hm[r] = h[r] * m;
+                p[r] = byte_of(pw, r);
+            }
+            double col[K][K], c[K], y[K];
+#pragma unroll
+            for (int jc = 0; jc < K; ++jc)
+#pragma unroll
+                for (int r = 0; r < K; ++r) col[jc][r] = (double)tabs[(hm[r] + p[jc]) * WTP + wl];
+            if (MODE == DM_VALUES) {
+#pragma unroll
+                for (int r = 0; r < K; ++r) c[r] = 0.0;
+                const double dd = SmallDet<K, double>::run(col, c, y);
+                Rg[(size_t)min(j + i, j1 - 1) * 64] = dd;
+                continue;
+            }
+#pragma unroll
+            for (int r = 0; r < K; ++r) c[r] = (double)cs[h[r] * WTP + wl];
+            const double dd = SmallDet<K, double>::run(col, c, y);
+            const double Cu = (j + i < j1) ? cb[i] : 0.0;
+            acc[0] = fma(Cu, dd, acc[0]);
+#pragma unroll
+            for (int jc = 0; jc < K; ++jc) {
+                const double wy = Cu * y[jc];
+#pragma unroll
+                for (int b = 0; b < NE; ++b)
+                    acc[1 + b] = fma((double)gs[(p[jc] * NE + b) * WTP + wl], wy, acc[1 + b]);
+            }
+        }
+    };
+    fetch(j0, hA, pA, cA);
+    for (int j = j0; j < j1; j += 2 * D) {
+        fetch(j + D, hB, pB, cB);
+        run_group(j, hA, pA, cA);
+        if (j + D >= j1) break;
+        fetch(j + 2 * D, hA, pA, cA);
+        run_group(j + D, hB, pB, cB);
+    }
+}
+
+// Orders above 4 on 64-walker tiles: one excitation at a time, elimination
+// with partial pivoting (det_one_generic).
+template <typename TT, int MODE>
+__device__ void det_generic64(const SpinDev &S, int tile, int k, int j0, int j1,
+                              const uint32_t *exw, int u0, const TT *__restrict__ tabs,
+                              const TT *__restrict__ gs, const TT *__restrict__ cs, int wl,
+                              double acc[NSUM]) {
+    const size_t cb0 = (size_t)tile * S.U * 64 + wl;
+    const auto Cg = MDE_G(double, S.C) + cb0;
+    const auto Rg = MDE_GW(double, S.R) + cb0;
+    const uint4 *exl = reinterpret_cast<const uint4 *>(exw);
+    for (int j = j0; j < j1; ++j) {
+        uint4 ex = exl[j - u0];
+        ex.x = __builtin_amdgcn_readfirstlane(ex.x);
+        ex.y = __builtin_amdgcn_readfirstlane(ex.y);
+        ex.z = __builtin_amdgcn_readfirstlane(ex.z);
+        ex.w = __builtin_amdgcn_readfirstlane(ex.w);
+        const double Cu = MODE == DM_PROPOSE ? Cg[(size_t)j * 64] : 0.0;
+        const double R = det_one_generic<TT, MODE>(k, ex, tabs, gs, cs, S.m, 65, wl, Cu, acc);
+        if (MODE == DM_VALUES) Rg[(size_t)j * 64] = R;
+    }
+}
+
+// Copy `count` = rows x WT elements of a walker-tiled array into padded LDS
+// rows (row stride WTP).  Each thread keeps eight loads in flight before it
+// writes, instead of one load-wait-store round trip per element.
+template <int WT, typename TT, typename ST>
+__device__ __forceinline__ void stage_rows(TT *__restrict__ dst, const ST __attribute__((address_space(1))) *src,
+                                           int count, int WTP, int tid, int nthr) {
+    constexpr int U = 8;
+    int idx = tid;
+    for (; idx + (U - 1) * nthr < count; idx += U * nthr) {
+        ST v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = src[idx + u * nthr];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = idx + u * nthr;
+            dst[(e / WT) * WTP + e % WT] = (TT)v[u];
+        }
+    }
+    for (; idx < count; idx += nthr) dst[(idx / WT) * WTP + idx % WT] = (TT)src[idx];
+}
+
 template <typename TT, int MODE, int WT>
 __global__ void __launch_bounds__(1024)
-k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int n_items,
+k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
+      const int32_t *__restrict__ bounds, ItemQueues qs,
       int ex_cap, const MoveArgs *__restrict__ moves, MoveArgs m1, int32_t *__restrict__ counter,
       const double *tab0, const double *tab1) {
     extern __shared__ uint4 smem4[];
@@ -282,12 +428,59 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
     const int nslot = nthr / WT;
     uint4 *exl = smem4;
     unsigned char *tab_raw = reinterpret_cast<unsigned char *>(smem4 + ex_cap);
+    // Items of queue x: the first (blocks on XCD x) are taken statically, one
+    // per block, without an atomic; the rest are claimed through counter[x].
+    // A block whose queue is drained claims from the other queues (their
+    // counters are read by eight lanes at once before any atomic is spent:
+    // device-scope atomics cross the dies and cost microseconds each).
+    const int home = blockIdx.x % NXCD, hb = blockIdx.x / NXCD;
+    auto blocks_on = [&](int x) { return ((int)gridDim.x - x + NXCD - 1) / NXCD; };
+    int stage = 0;   // 0: static item, 1: home queue, 2: other queues, 3: none left
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&counter[0], 1);
+        if (tid < 64) {
+            const int lane = tid;
+            int got = -1;
+            if (stage == 0) {
+                stage = 1;
+                if (hb < qs.off[home + 1] - qs.off[home]) got = qs.off[home] + hb;
+            }
+            if (got < 0 && stage == 1) {
+                const int nb = blocks_on(home), sz = qs.off[home + 1] - qs.off[home];
+                if (nb < sz) {
+                    int k = 0;
+                    if (lane == 0) k = atomicAdd(&counter[home], 1);
+                    k = __shfl(k, 0, 64);
+                    if (nb + k < sz) got = qs.off[home] + nb + k;
+                }
+                if (got < 0) stage = 2;
+            }
+            if (got < 0 && stage == 2) {
+                int avail = 0, x = 0, nb = 0, sz = 0;
+                if (lane < NXCD - 1) {
+                    x = (home + 1 + lane) % NXCD;
+                    nb = blocks_on(x);
+                    sz = qs.off[x + 1] - qs.off[x];
+                    if (nb < sz)
+                        avail = nb + __hip_atomic_load(&counter[x], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) < sz;
+                }
+                unsigned long long mask = __ballot(avail);
+                while (mask != 0ull && got < 0) {
+                    const int q = __ffsll((long long)mask) - 1;
+                    const int qx = __shfl(x, q, 64), qnb = __shfl(nb, q, 64), qsz = __shfl(sz, q, 64);
+                    int k = 0;
+                    if (lane == 0) k = atomicAdd(&counter[qx], 1);
+                    k = __shfl(k, 0, 64);
+                    if (qnb + k < qsz) got = qs.off[qx] + qnb + k;
+                    mask &= mask - 1ull;
+                }
+                if (got < 0) stage = 3;
+            }
+            if (lane == 0) s_item = got;
+        }
+        __syncthreads();        const int gi = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
-        const int gi = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (gi >= n_items) break;
+        if (gi < 0) break;
         WorkItem it = items[gi];
         it.inst = __builtin_amdgcn_readfirstlane(it.inst);
         it.spin = __builtin_amdgcn_readfirstlane(it.spin);
@@ -296,6 +489,7 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
         it.u0 = __builtin_amdgcn_readfirstlane(it.u0);
         it.u1 = __builtin_amdgcn_readfirstlane(it.u1);
         it.slot = __builtin_amdgcn_readfirstlane(it.slot);
+        it.wb = __builtin_amdgcn_readfirstlane(it.wb);
         const InstDev &I = insts[it.inst];
         const SpinDev &S = I.s[it.spin];
         if (MODE == DM_PROPOSE) {
@@ -309,13 +503,13 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
         TT *cs = gs + NE * m * WTP;
         const int w0 = it.tile * WT;
         const int nm = n * m;
-        const bool runs = (WT == 64) && it.order >= 1 && it.order <= 4;
+        const bool runs = WT == 64;
         // ---- stage the excitation records and the walker tile's tables ----
-        if (!runs) {
+        uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
+        {
             // records as 4 x 32-bit words (global loads)
             const auto exg = MDE_G(uint32_t, S.ex) + (size_t)it.u0 * 4;
-            uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
-            for (int idx = tid; idx < (it.u1 - it.u0) * 4; idx += nthr) exw[idx] = exg[idx];
+            stage_rows<1>(exw, exg, (it.u1 - it.u0) * 4, 1, tid, nthr);
         }
         // tables are stored walker-tiled ([tile][e][WT]): straight copies into
         // the padded LDS rows, no index division
@@ -323,25 +517,13 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
             const size_t tn = (size_t)it.tile * nm * WT, tg = (size_t)it.tile * NE * m * WT,
                          tc = (size_t)it.tile * n * WT;
             if (sizeof(TT) == 8) {
-                const auto Tg = MDE_G(double, S.T) + tn;
-                const auto gg = MDE_G(double, I.ev) + tg;
-                const auto cg = MDE_G(double, I.cc) + tc;
-                for (int idx = tid; idx < nm * WT; idx += nthr)
-                    tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
-                for (int idx = tid; idx < NE * m * WT; idx += nthr)
-                    gs[(idx / WT) * WTP + idx % WT] = (TT)gg[idx];
-                for (int idx = tid; idx < n * WT; idx += nthr)
-                    cs[(idx / WT) * WTP + idx % WT] = (TT)cg[idx];
+                stage_rows<WT>(tabs, MDE_G(double, S.T) + tn, nm * WT, WTP, tid, nthr);
+                stage_rows<WT>(gs, MDE_G(double, I.ev) + tg, NE * m * WT, WTP, tid, nthr);
+                stage_rows<WT>(cs, MDE_G(double, I.cc) + tc, n * WT, WTP, tid, nthr);
             } else {
-                const auto Tg = MDE_G(float, I.Tp32) + tn;
-                const auto gg = MDE_G(float, I.ev32) + tg;
-                const auto cg = MDE_G(float, I.cc32) + tc;
-                for (int idx = tid; idx < nm * WT; idx += nthr)
-                    tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
-                for (int idx = tid; idx < NE * m * WT; idx += nthr)
-                    gs[(idx / WT) * WTP + idx % WT] = (TT)gg[idx];
-                for (int idx = tid; idx < n * WT; idx += nthr)
-                    cs[(idx / WT) * WTP + idx % WT] = (TT)cg[idx];
+                stage_rows<WT>(tabs, MDE_G(float, I.Tp32) + tn, nm * WT, WTP, tid, nthr);
+                stage_rows<WT>(gs, MDE_G(float, I.ev32) + tg, NE * m * WT, WTP, tid, nthr);
+                stage_rows<WT>(cs, MDE_G(float, I.cc32) + tc, n * WT, WTP, tid, nthr);
             }
         } else {
             const double *tabd = it.spin == 0 ? tab0 : tab1;
@@ -353,30 +535,28 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
                 }
             } else {
                 const size_t tn = (size_t)it.tile * nm * WT;
-                if (sizeof(TT) == 8) {
-                    const auto Tg = MDE_G(double, S.T) + tn;
-                    for (int idx = tid; idx < nm * WT; idx += nthr)
-                        tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
-                } else {
-                    const auto Tg = MDE_G(float, S.T32) + tn;
-                    for (int idx = tid; idx < nm * WT; idx += nthr)
-                        tabs[(idx / WT) * WTP + idx % WT] = (TT)Tg[idx];
-                }
+                if (sizeof(TT) == 8)
+                    stage_rows<WT>(tabs, MDE_G(double, S.T) + tn, nm * WT, WTP, tid, nthr);
+                else
+                    stage_rows<WT>(tabs, MDE_G(float, S.T32) + tn, nm * WT, WTP, tid, nthr);
             }
         }
         __syncthreads();
         double acc[NSUM] = {0, 0, 0, 0, 0, 0};
         if (runs) {
-            // wave `slot` takes a contiguous share of the item's excitations
-            const int len = it.u1 - it.u0;
+            // wave `slot` takes its cost-balanced range of the item, order by order
             const int ws = __builtin_amdgcn_readfirstlane(slot);
-            const int j0 = it.u0 + (int)(((long long)ws * len) / nslot);
-            const int j1 = it.u0 + (int)(((long long)(ws + 1) * len) / nslot);
-            switch (it.order) {
-                case 1: det_runs64<1, TT, MODE>(S, it.tile, j0, j1, tabs, gs, cs, wl, acc); break;
-                case 2: det_runs64<2, TT, MODE>(S, it.tile, j0, j1, tabs, gs, cs, wl, acc); break;
-                case 3: det_runs64<3, TT, MODE>(S, it.tile, j0, j1, tabs, gs, cs, wl, acc); break;
-                default: det_runs64<4, TT, MODE>(S, it.tile, j0, j1, tabs, gs, cs, wl, acc); break;
+            const int j0 = bounds[it.wb + ws], j1 = bounds[it.wb + ws + 1];
+            for (int k = 1; k <= S.max_order; ++k) {
+                const int a = max(j0, S.order_start[k]), b = min(j1, S.order_start[k + 1]);
+                if (a >= b) continue;
+                switch (k) {
+                    case 1: det_runs64<1, TT, MODE>(S, it.tile, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
+                    case 2: det_runs64<2, TT, MODE>(S, it.tile, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
+                    case 3: det_direct64<3, TT, MODE>(S, it.tile, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
+                    case 4: det_direct64<4, TT, MODE>(S, it.tile, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
+                    default: det_generic64<TT, MODE>(S, it.tile, k, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
+                }
             }
         } else {
             switch (it.order) {
@@ -413,20 +593,21 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items, int
             __syncthreads();
         }
     }
-    // the last block out resets the queue for the next launch
+    // the last block out resets the queues for the next launch
     if (tid == 0) {
         __threadfence();
-        const int done = atomicAdd(&counter[1], 1);
+        const int done = atomicAdd(&counter[NXCD], 1);
         if (done == (int)gridDim.x - 1) {
-            atomicExch(&counter[0], 0);
-            atomicExch(&counter[1], 0);
+            for (int x = 0; x <= NXCD; ++x)
+                __hip_atomic_store(&counter[x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
 
 template <typename TT, int MODE>
 static hipError_t launch_det_wt(int WT, hipStream_t st, const InstDev *d_insts,
-                                const WorkItem *items, int n_items, int ex_cap,
+                                const WorkItem *items, const int32_t *bounds,
+                                const ItemQueues &qs, int ex_cap,
                                 const MoveArgs *d_moves, const MoveArgs &m1, size_t lds,
                                 int threads, int grid, int32_t *counter, const double *t0,
                                 const double *t1) {
@@ -436,7 +617,7 @@ static hipError_t launch_det_wt(int WT, hipStream_t st, const InstDev *d_insts,
         if (lds > 65536)                                                                    \
             (void)hipFuncSetAttribute((const void *)fn,                                     \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds, st, d_insts, items, n_items,  \
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds, st, d_insts, items, bounds, qs, \
                            ex_cap, d_moves, m1, counter, t0, t1);                           \
         return hipGetLastError();                                                           \
     }
@@ -454,23 +635,23 @@ static hipError_t launch_det_wt(int WT, hipStream_t st, const InstDev *d_insts,
 }
 
 hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst, const WorkItem *items,
-                      int n_items, int ex_cap, const MoveArgs *d_moves, const MoveArgs &m1, int mode,
-                      int prec, int WT, size_t lds, int threads, int grid, int32_t *counter,
-                      const double *tab0, const double *tab1) {
+                      const int32_t *bounds, const ItemQueues &qs, int ex_cap, const MoveArgs *d_moves, const MoveArgs &m1,
+                      int mode, int prec, int WT, size_t lds, int threads, int grid,
+                      int32_t *counter, const double *tab0, const double *tab1) {
     // every instance of one launch uses the same walker tile WT
     (void)n_inst;
-    if (n_items <= 0) return hipSuccess;
+    if (qs.off[NXCD] <= 0) return hipSuccess;
     if (prec == 0) {
         if (mode == DM_PROPOSE)
-            return launch_det_wt<double, DM_PROPOSE>(WT, st, d_insts, items, n_items, ex_cap, d_moves,
+            return launch_det_wt<double, DM_PROPOSE>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves,
                                                      m1, lds, threads, grid, counter, tab0, tab1);
-        return launch_det_wt<double, DM_VALUES>(WT, st, d_insts, items, n_items, ex_cap, d_moves, m1,
+        return launch_det_wt<double, DM_VALUES>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves, m1,
                                                 lds, threads, grid, counter, tab0, tab1);
     }
     if (mode == DM_PROPOSE)
-        return launch_det_wt<float, DM_PROPOSE>(WT, st, d_insts, items, n_items, ex_cap, d_moves, m1,
+        return launch_det_wt<float, DM_PROPOSE>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves, m1,
                                                 lds, threads, grid, counter, tab0, tab1);
-    return launch_det_wt<float, DM_VALUES>(WT, st, d_insts, items, n_items, ex_cap, d_moves, m1,
+    return launch_det_wt<float, DM_VALUES>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves, m1,
                                            lds, threads, grid, counter, tab0, tab1);
 }
 
@@ -699,7 +880,20 @@ __global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__re
     double sum[NSUM] = {C0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
     const auto part = MDE_G(double, S.partial);
-    for (int s = s0; s < s1; ++s) {
+    // slots in order; the loads of four slots are issued before they are added
+    int s = s0;
+    for (; s + 4 <= s1; s += 4) {
+        double v[4][NSUM];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) v[k][q] = part[((size_t)(s + k) * WT + wl) * NSUM + q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) sum[q] += v[k][q];
+    }
+    for (; s < s1; ++s) {
 #pragma unroll
         for (int q = 0; q < NSUM; ++q) sum[q] += part[((size_t)s * WT + wl) * NSUM + q];
     }

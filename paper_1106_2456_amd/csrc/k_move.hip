@@ -218,13 +218,13 @@ __host__ __device__ inline int odd_stride(int x) { return x | 1; }
 template <int WT, typename TT>
 __global__ void __launch_bounds__(256)
 k_propose(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1,
-          int split) {
+          int split, int T8, int n_inst) {
     constexpr bool F64 = sizeof(TT) == 8;
-    const int inst = blockIdx.y;
+    int inst, t, part;
+    if (!tile_of_block(split, T8, n_inst, inst, t, part)) return;
     const InstDev &I = insts[inst];
     const MoveArgs mv = moves ? moves[inst] : m1;
     const SpinDev &S = I.s[mv.spin];
-    const int t = blockIdx.x / split, part = blockIdx.x % split;
     if (t >= S.n_tiles) return;
     const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nn = n * n;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -237,10 +237,25 @@ k_propose(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves,
     double *c_s = o_s + WT * ost;              // [n][WT]: c = A^-1 e_i
     double *r_s = c_s + n * WT;                // [5][WT]: 1/rho, kappa^a / rho (mixed)
     const auto orb = MDE_G(double, mv.new_orb) + (size_t)w0 * 5 * no;
-    for (int idx = tid; idx < nw * 5 * ns; idx += nthr) {
-        const int l = idx / (5 * ns), r = idx - l * 5 * ns, a = r / ns, j = r - a * ns;
-        const int p = j < n ? j : p0 + j;      // orbital index (virtual p0.. at n + p0)
-        o_s[l * ost + r] = orb[(size_t)l * 5 * no + a * no + p];
+    {
+        // four loads per thread in flight before the LDS writes
+        const int tot = nw * 5 * ns;
+        int idx = tid;
+        for (; idx < tot; idx += 4 * nthr) {
+            double v[4];
+            int o[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int id = min(idx + u * nthr, tot - 1);
+                const int l = id / (5 * ns), r = id - l * 5 * ns, a = r / ns, j = r - a * ns;
+                const int p = j < n ? j : p0 + j;  // orbital index (virtual p0.. at n + p0)
+                o[u] = l * ost + r;
+                v[u] = orb[(size_t)l * 5 * no + a * no + p];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (idx + u * nthr < tot) o_s[o[u]] = v[u];
+        }
     }
     const auto Bg = MDE_G(double, S.B) + (size_t)w0 * nn;
     for (int idx = tid; idx < n * WT; idx += nthr) {
@@ -286,6 +301,7 @@ k_propose(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves,
             double r = 0.0;
             if (l < nw) {
                 const double *ol = o_s + l * ost;
+#pragma unroll 4
                 for (int k = 0; k < n; ++k) r = fma(ol[k], Bg[(size_t)l * nn + k * n + j], r);
                 r -= (j == row) ? 1.0 : 0.0;
             }
@@ -308,6 +324,7 @@ k_propose(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves,
         if (l < nw) {
             const double *ol = o_s + l * ost;
             double v = 0.0, da[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
             for (int r = 0; r < n; ++r) {
                 const double tv = (double)Tt[(size_t)(r * m + p) * WT + l];
                 v = fma(ol[r], tv, v);
@@ -498,7 +515,8 @@ hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, in
         return hipGetLastError();
     }
     const size_t lds = propose_lds(nmax, mmax, WT, split);
-    dim3 g(max_tiles * split, n_inst);
+    const int T8 = (max_tiles + NXCD - 1) / NXCD * NXCD;
+    dim3 g(n_inst * T8 * split);
 #define MDE_PP(X)                                                                              \
     case X:                                                                                    \
         if (prec == 0) {                                                                       \
@@ -506,13 +524,13 @@ hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, in
                 (void)hipFuncSetAttribute((const void *)k_propose<X, double>,                  \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
             hipLaunchKernelGGL((k_propose<X, double>), g, dim3(256), lds, st, d_insts, d_moves, \
-                               m1, split);                                                     \
+                               m1, split, T8, n_inst);                                         \
         } else {                                                                               \
             if (lds > 65536)                                                                   \
                 (void)hipFuncSetAttribute((const void *)k_propose<X, float>,                   \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
             hipLaunchKernelGGL((k_propose<X, float>), g, dim3(256), lds, st, d_insts, d_moves, \
-                               m1, split);                                                     \
+                               m1, split, T8, n_inst);                                         \
         }                                                                                      \
         break;
     switch (WT) {
@@ -541,61 +559,100 @@ int propose_split_limit(int nmax, int mmax, int WT, size_t lds_max) {
 template <int WT>
 __global__ void __launch_bounds__(256)
 k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, MoveArgs m1,
-         int split) {
-    const int inst = blockIdx.y;
+         int split, int T8, int n_inst) {
+    int inst, t, part;
+    if (!tile_of_block(split, T8, n_inst, inst, t, part)) return;
     const InstDev &I = insts[inst];
     const MoveArgs mv = moves ? moves[inst] : m1;
     const SpinDev &S = I.s[mv.spin];
-    const int t = blockIdx.x / split, part = blockIdx.x % split;
     if (t >= S.n_tiles) return;
-    const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nm = n * m;
+    const int n = S.n, m = S.m, no = S.no, row = mv.row, W = I.W, nm = n * m, nn = n * n;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int w0 = t * WT, nw = min(WT, W - w0);
     __shared__ int acc_s[64];
-    __shared__ double ir_s[64];
-    if (tid < WT) {
-        const int w = t * WT + tid;
-        const int a = (w < W) ? (int)mv.accept[w] : 0;
-        acc_s[tid] = a;
-        ir_s[tid] = a ? 1.0 / I.rho[w] : 0.0;
+    extern __shared__ double sha[];
+    double *cp_s = sha;            // [n][WT]  c' = c / rho (0 for rejected walkers)
+    double *rr_s = sha + n * WT;   // [n][WT]  a'^T A^-1 - e_i^T
+    if (tid < WT) acc_s[tid] = (tid < nw) ? (int)mv.accept[w0 + tid] : 0;
+    __syncthreads();
+    {
+        const auto cc = MDE_G(double, I.cc) + (size_t)t * n * WT;
+        const auto rr = MDE_G(double, I.rrow) + (size_t)t * n * WT;
+        for (int idx = tid; idx < n * WT; idx += nthr) {
+            const int l = idx % WT;
+            const double c = cc[idx], r = rr[idx];
+            const double ir = acc_s[l] ? 1.0 / I.rho[w0 + l] : 0.0;
+            cp_s[idx] = c * ir;
+            rr_s[idx] = r;
+        }
     }
     __syncthreads();
-    const auto nrow = MDE_G(double, I.newrow);
-    const auto rr = MDE_G(double, I.rrow) + (size_t)t * n * WT;
-    const auto cc = MDE_G(double, I.cc) + (size_t)t * n * WT;
-    // A^-1 rows of this part (the update row was formed from the pre-update
-    // inverse by the proposal)
-    const int rc = (n + split - 1) / split, r0 = part * rc, r1 = min(n, r0 + rc);
-    for (int idx = r0 * n * WT + tid; idx < r1 * n * WT; idx += nthr) {
-        const int l = idx % WT, rj = idx / WT, r = rj / n, j = rj - r * n;
-        if (!acc_s[l]) continue;
-        const size_t o = ((size_t)(t * WT + l) * n + r) * n + j;
-        S.B[o] = fma(-cc[r * WT + l] * ir_s[l], rr[j * WT + l], S.B[o]);
+    // A^-1 of the tile's walkers is contiguous: the part takes a slice of it
+    {
+        const int tot = nw * nn, ch = (tot + split - 1) / split;
+        const int e0 = part * ch, e1 = min(tot, e0 + ch);
+        double *Bt = S.B + (size_t)w0 * nn;
+        for (int idx = e0 + tid; idx < e1; idx += nthr) {
+            const int l = idx / nn, rj = idx - l * nn, r = rj / n, j = rj - r * n;
+            if (!acc_s[l]) continue;
+            Bt[idx] = fma(-cp_s[r * WT + l], rr_s[j * WT + l], Bt[idx]);
+        }
     }
     const size_t tb = (size_t)t * nm * WT;
     const int ec = (nm * WT + split - 1) / split, e0 = part * ec, e1 = min(nm * WT, e0 + ec);
     if (I.prec == 0) {
         const auto qv = MDE_G(double, I.ev) + (size_t)t * 5 * m * WT;
-        for (int idx = e0 + tid; idx < e1; idx += nthr) {
+        int idx = e0 + tid;
+        // four entries per thread in flight
+        for (; idx + 3 * nthr < e1; idx += 4 * nthr) {
+            double tv[4], qp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int id = idx + u * nthr, l = id % WT, e = id / WT, r = e / m, p = e - r * m;
+                tv[u] = S.T[tb + id];
+                qp[u] = qv[(size_t)p * 5 * WT + l];
+                (void)r;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int id = idx + u * nthr, l = id % WT, e = id / WT, r = e / m;
+                if (acc_s[l]) S.T[tb + id] = fma(-cp_s[r * WT + l], qp[u], tv[u]);
+            }
+        }
+        for (; idx < e1; idx += nthr) {
             const int l = idx % WT;
             if (!acc_s[l]) continue;
             const int e = idx / WT, r = e / m, p = e - r * m;
-            const double cr = cc[r * WT + l] * ir_s[l], qp = qv[(size_t)p * 5 * WT + l];
-            S.T[tb + idx] = fma(-cr, qp, S.T[tb + idx]);
+            S.T[tb + idx] = fma(-cp_s[r * WT + l], qv[(size_t)p * 5 * WT + l], S.T[tb + idx]);
         }
     } else {
-        for (int idx = e0 + tid; idx < e1; idx += nthr)
+        int idx = e0 + tid;
+        for (; idx + 3 * nthr < e1; idx += 4 * nthr) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = I.Tp32[tb + idx + u * nthr];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (acc_s[(idx + u * nthr) % WT]) S.T32[tb + idx + u * nthr] = v[u];
+        }
+        for (; idx < e1; idx += nthr)
             if (acc_s[idx % WT]) S.T32[tb + idx] = I.Tp32[tb + idx];
     }
-    const int nc = (no + split - 1) / split, q0 = part * nc, q1 = min(no, q0 + nc);
-    for (int idx = q0 * WT + tid; idx < q1 * WT; idx += nthr) {
-        const int p = idx / WT, l = idx % WT, w = t * WT + l;
-        if (!acc_s[l]) continue;
-        const double v = nrow[(size_t)w * I.nomax + p];
-        S.Phi[((size_t)w * n + row) * no + p] = v;
-        if (I.prec == 2 && p >= n) S.PhiV32[((size_t)w * n + row) * m + (p - n)] = (float)v;
+    // orbital row of the moved electron (walker-major, contiguous per walker)
+    {
+        const int tot = nw * no, ch = (tot + split - 1) / split;
+        const int q0 = part * ch, q1 = min(tot, q0 + ch);
+        const auto nrow = MDE_G(double, I.newrow);
+        for (int idx = q0 + tid; idx < q1; idx += nthr) {
+            const int l = idx / no, p = idx - l * no, w = w0 + l;
+            if (!acc_s[l]) continue;
+            const double v = nrow[(size_t)w * I.nomax + p];
+            S.Phi[((size_t)w * n + row) * no + p] = v;
+            if (I.prec == 2 && p >= n) S.PhiV32[((size_t)w * n + row) * m + (p - n)] = (float)v;
+        }
     }
-    if (part == 0 && tid < WT && acc_s[tid]) {
-        const int w = t * WT + tid;
+    if (part == 0 && tid < nw && acc_s[tid]) {
+        const int w = w0 + tid;
         const double rho = I.rho[w];
         S.logdet[w] += log(fabs(rho));
         if (rho < 0.0) S.sgn[w] = -S.sgn[w];
@@ -606,17 +663,20 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
 hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
                          int mmax, int WT, int max_tiles, int split) {
-    dim3 g(max_tiles * split, n_inst);
+    const int T8 = (max_tiles + NXCD - 1) / NXCD * NXCD;
+    dim3 g(n_inst * T8 * split);
+    const size_t lds = sizeof(double) * 2 * (size_t)nmax * WT;
 #define MDE_AC(X)                                                                              \
     case X:                                                                                    \
-        hipLaunchKernelGGL(k_accept<X>, g, dim3(256), 0, st, d_insts, d_moves, m1, split);    \
+        hipLaunchKernelGGL(k_accept<X>, g, dim3(256), lds, st, d_insts, d_moves, m1, split,   \
+                           T8, n_inst);                                                        \
         break;
     switch (WT) {
         MDE_AC(1) MDE_AC(2) MDE_AC(4) MDE_AC(8) MDE_AC(16) MDE_AC(32) MDE_AC(64)
         default: return hipErrorInvalidValue;
     }
 #undef MDE_AC
-    (void)prec; (void)maxW; (void)nmax; (void)mmax;
+    (void)prec; (void)maxW; (void)mmax;
     return hipGetLastError();
 }
 
@@ -636,7 +696,7 @@ __global__ void k_init_misc(const InstDev *__restrict__ insts) {
         }
     }
     if (tid < (size_t)I.W) I.st[tid] = 0;
-    if (tid < 2) I.counter[tid] = 0;
+    if (tid < 16) I.counter[tid] = 0;
 }
 
 hipError_t launch_init_misc(hipStream_t st, const InstDev *d_inst, const InstDev &h) {
@@ -702,7 +762,7 @@ hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int32_t v, size_t n) {
 }
 
 hipError_t launch_reset_counter(hipStream_t st, int32_t *counter) {
-    return launch_fill_i32(st, counter, 0, 2);
+    return launch_fill_i32(st, counter, 0, 16);
 }
 
 // ---------------------------------------------------------------------------

@@ -45,7 +45,10 @@ struct SpinHost {
     std::vector<int> inv_off, inv_ent;
     // plan
     int item_exc = 0, threads = 0;
-    std::vector<WorkItem> items;     // scheduling order
+    std::vector<double> ucost;       // cost of each excitation in the 64-walker kernel
+    std::vector<WorkItem> items;     // scheduling order, grouped by XCD queue
+    std::vector<int32_t> bounds;     // per item (64-walker tiles): wave range boundaries
+    ItemQueues queues{};
     std::vector<int> tile_slot;
     size_t lds_prop = 0, lds_val = 0;
     int grid = 0;
@@ -90,6 +93,8 @@ struct mde_ctx {
     int32_t *d_perm_user[2] = {nullptr, nullptr};
     WorkItem *d_items[2] = {nullptr, nullptr};
     int32_t *d_tile_slot[2] = {nullptr, nullptr};
+    int32_t *d_bounds[2] = {nullptr, nullptr};
+    size_t bounds_cap[2] = {0, 0};
     size_t items_cap[2] = {0, 0};
     size_t partial_cap[2] = {0, 0};
     size_t tileslot_cap[2] = {0, 0};
@@ -123,7 +128,9 @@ struct mde_group {
     InstDev *d_insts = nullptr;
     MoveArgs *d_moves = nullptr;
     WorkItem *d_items = nullptr;
+    int32_t *d_bounds = nullptr;
     int n_items = 0;
+    ItemQueues queues{};
     std::vector<MoveArgs> hmoves;
     // pinned upload ring
     static constexpr int RING = 64;
@@ -181,6 +188,32 @@ static double order_cost(int k) {
     return c[std::min(std::max(k, 0), 8)];
 }
 
+// Relative cost of each excitation in the 64-walker determinant kernel (one
+// wave per excitation), measured in units of one excitation inside a run:
+// orders 1 and 2 are evaluated in runs that share holes and leading
+// particles (a new run pays for its cofactors), orders 3 and 4 one by one.
+static void excitation_costs(SpinHost &sp) {
+    const int U = (int)sp.ex.size();
+    sp.ucost.assign(U, 0.0);
+    for (int u = 1; u < U; ++u) {
+        const int k = sp.orders[u];
+        double w;
+        if (k <= 2) {
+            const uint32_t pmask = k == 1 ? 0u : 0xffu;
+            const bool fresh = sp.orders[u - 1] != k || sp.ex[u].x != sp.ex[u - 1].x ||
+                               ((sp.ex[u].z ^ sp.ex[u - 1].z) & pmask) != 0u;
+            w = 1.0 + (fresh ? (k == 1 ? 0.5 : 1.5) : 0.0);
+        } else if (k == 3) {
+            w = 2.0;
+        } else if (k == 4) {
+            w = 5.0;
+        } else {
+            w = 4.0 * k * k;
+        }
+        sp.ucost[u] = w;
+    }
+}
+
 static int spin_of(const mde_ctx *c, int e, int *row) {
     if (e < c->d.n_elec[0]) {
         *row = e;
@@ -204,64 +237,157 @@ static size_t det_lds(const SpinHost &s, int WT, int threads, int prec, bool pro
 
 // work items of one spin for a plan: per tile, per order, chunks of about
 // item_exc order-2-equivalent excitations (at least one per slot)
-static void build_items(const SpinHost &s, int W, int WT, int item_exc, int threads,
-                        std::vector<WorkItem> &items, std::vector<int> &tile_slot, int spin) {
+static ItemQueues queue_order(std::vector<WorkItem> &items, const std::vector<double> &cost);
+
+// boundaries of nslot wave ranges of about equal cost over [u0, u1)
+static void wave_bounds(const SpinHost &s, int u0, int u1, int nslot, std::vector<int32_t> &out) {
+    double tot = 0.0;
+    for (int u = u0; u < u1; ++u) tot += s.ucost[u];
+    out.push_back(u0);
+    double acc = 0.0;
+    int u = u0;
+    for (int w = 1; w < nslot; ++w) {
+        const double target = tot * w / nslot;
+        while (u < u1 && acc + 0.5 * s.ucost[u] < target) acc += s.ucost[u++];
+        out.push_back(u);
+    }
+    out.push_back(u1);
+}
+
+static ItemQueues build_items(const SpinHost &s, int W, int WT, int item_exc, int threads,
+                              std::vector<WorkItem> &items, std::vector<int> &tile_slot, int spin,
+                              std::vector<int32_t> *bounds = nullptr) {
     items.clear();
+    if (bounds) bounds->clear();
     const int n_tiles = (W + WT - 1) / WT;
     tile_slot.assign(n_tiles + 1, 0);
     const int nslot = threads / WT;
     std::vector<WorkItem> per;
     std::vector<double> cost;
-    for (int t = 0; t < n_tiles; ++t) {
-        tile_slot[t] = (int)per.size();
-        for (int k = 1; k <= s.max_order; ++k) {
-            const int a = s.order_start[k], b = s.order_start[k + 1];
-            if (b <= a) continue;
-            int chunk = (int)std::lround(item_exc * order_cost(2) / order_cost(k));
-            chunk = std::min(std::max(chunk, nslot), ITEM_MAX);
-            for (int u = a; u < b; u += chunk) {
+    const int U = s.order_start[MAXK + 1];
+    if (WT == 64) {
+        // 64-walker tiles: contiguous ranges of the sorted excitation list
+        // (orders mixed) of about equal cost, each split into equal-cost
+        // wave ranges
+        std::vector<double> cum(U + 1, 0.0);
+        for (int u = 1; u < U; ++u) cum[u + 1] = cum[u] + s.ucost[u];
+        const double total = cum[U];
+        int n_it = std::max(1, (int)std::lround(total / std::max(item_exc, 1)));
+        n_it = std::max(n_it, (U - 1 + ITEM_MAX - 1) / ITEM_MAX);
+        std::vector<int> cuts(n_it + 1, 1);
+        cuts[n_it] = U;
+        for (int i = 1; i < n_it; ++i) {
+            const double target = total * i / n_it;
+            int u = (int)(std::lower_bound(cum.begin() + 1, cum.begin() + U + 1, target) - cum.begin());
+            cuts[i] = std::min(std::max(u, cuts[i - 1]), U);
+        }
+        // respect the LDS record capacity
+        for (int i = 1; i <= n_it; ++i)
+            if (cuts[i] - cuts[i - 1] > ITEM_MAX) cuts[i] = cuts[i - 1] + ITEM_MAX;
+        if (U > 1 && cuts[n_it] < U) {
+            while (cuts.back() < U) cuts.push_back(std::min(U, cuts.back() + ITEM_MAX));
+            n_it = (int)cuts.size() - 1;
+        }
+        for (int t = 0; t < n_tiles; ++t) {
+            tile_slot[t] = (int)per.size();
+            for (int i = 0; i < n_it; ++i) {
+                const int u0 = cuts[i], u1 = cuts[i + 1];
+                if (u1 <= u0) continue;
                 WorkItem it{};
                 it.inst = 0;
                 it.spin = spin;
                 it.tile = t;
-                it.order = k;
-                it.u0 = u;
-                it.u1 = std::min(b, u + chunk);
+                it.order = 0;
+                it.u0 = u0;
+                it.u1 = u1;
                 it.slot = (int)per.size();
+                it.wb = -1;
+                if (bounds) {
+                    it.wb = (int)bounds->size();
+                    wave_bounds(s, u0, u1, nslot, *bounds);
+                }
                 per.push_back(it);
-                cost.push_back(order_cost(k) * (it.u1 - it.u0));
+                cost.push_back(cum[u1] - cum[u0]);
+            }
+        }
+    } else {
+        for (int t = 0; t < n_tiles; ++t) {
+            tile_slot[t] = (int)per.size();
+            for (int k = 1; k <= s.max_order; ++k) {
+                const int a = s.order_start[k], b = s.order_start[k + 1];
+                if (b <= a) continue;
+                int chunk = (int)std::lround(item_exc * order_cost(2) / order_cost(k));
+                chunk = std::min(std::max(chunk, nslot), ITEM_MAX);
+                for (int u = a; u < b; u += chunk) {
+                    WorkItem it{};
+                    it.inst = 0;
+                    it.spin = spin;
+                    it.tile = t;
+                    it.order = k;
+                    it.u0 = u;
+                    it.u1 = std::min(b, u + chunk);
+                    it.slot = (int)per.size();
+                    it.wb = -1;
+                    per.push_back(it);
+                    cost.push_back(order_cost(k) * (it.u1 - it.u0));
+                }
             }
         }
     }
     tile_slot[n_tiles] = (int)per.size();
-    // scheduling order: most expensive first (the queue hands them out in order)
-    std::vector<int> idx(per.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    items.reserve(per.size());
-    for (int i : idx) items.push_back(per[i]);
+    items = per;
+    return queue_order(items, cost);
 }
 
-// total order-2-equivalent cost of one walker tile of a spin
-static double tile_cost(const SpinHost &sp) {
+// queue order: by XCD of the tile (t % 8), most expensive first inside a
+// queue (the queue hands them out in order)
+static ItemQueues queue_order(std::vector<WorkItem> &items, const std::vector<double> &cost) {
+    std::vector<int> idx(items.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+        const int qx = items[x].tile % NXCD, qy = items[y].tile % NXCD;
+        if (qx != qy) return qx < qy;
+        return cost[x] > cost[y];
+    });
+    std::vector<WorkItem> out;
+    out.reserve(items.size());
+    ItemQueues q{};
+    for (int i : idx) {
+        out.push_back(items[i]);
+        q.off[items[i].tile % NXCD + 1]++;
+    }
+    for (int x = 0; x < NXCD; ++x) q.off[x + 1] += q.off[x];
+    items.swap(out);
+    return q;
+}
+
+// cost of one walker tile of a spin, in the units of the item size: the
+// 64-walker kernel's excitation costs, else order-2-equivalent excitations
+static double tile_cost(const SpinHost &sp, int WT) {
     double t = 0.0;
+    if (WT == 64) {
+        for (double w : sp.ucost) t += w;
+        return t;
+    }
     for (int k = 1; k <= sp.max_order; ++k)
         t += order_cost(k) / order_cost(2) * (sp.order_start[k + 1] - sp.order_start[k]);
     return t;
 }
 
-// excitations per work item so that the whole launch has about
-// `waves_of_items` rounds of blocks over the CUs (fewer, larger items mean
-// fewer re-stagings of the walker tile's table in LDS)
+// item size so that the launch has about one round of items over the CUs
+// (fewer, larger items mean fewer re-stagings of the walker tile's tables
+// in LDS; the 64-walker items are cost-balanced, smaller tiles' items are
+// single-order and need more rounds to balance)
 static int item_size_for(const mde_ctx *c, const SpinHost &sp, int W, int WT, int threads,
                          size_t lds) {
     const int n_tiles = (W + WT - 1) / WT;
     int per_cu = (int)std::min<size_t>(160 * 1024 / std::max<size_t>(lds, 1024), 2048 / threads);
     per_cu = std::max(per_cu, 1);
-    const double target_items = 2.0 * c->n_cu * per_cu;
+    const double rounds = WT == 64 ? 1.0 : 2.0;
+    const double target_items = rounds * c->n_cu * per_cu;
     const double items_per_tile = std::max(1.0, target_items / n_tiles);
     const int nslot = threads / WT;
-    const int sz = (int)std::ceil(tile_cost(sp) / items_per_tile);
+    const int sz = (int)std::ceil(tile_cost(sp, WT) / items_per_tile);
     return std::max(sz, 4 * nslot);
 }
 
@@ -340,24 +466,29 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
     InstDev *d_inst = cv.take<InstDev>(1);
     // plan-dependent sizes: the maximum over candidate plans
     size_t max_items[2] = {0, 0}, max_partial[2] = {0, 0}, max_tiles[2] = {0, 0};
+    size_t max_bounds[2] = {0, 0};
     for (const Plan &p : candidate_plans(c, W)) {
         for (int s = 0; s < 2; ++s) {
             std::vector<WorkItem> it;
             std::vector<int> ts;
-            build_items(c->sp[s], W, p.WT, p.item_exc[s], p.threads[s], it, ts, s);
+            std::vector<int32_t> bd;
+            build_items(c->sp[s], W, p.WT, p.item_exc[s], p.threads[s], it, ts, s, &bd);
             max_items[s] = std::max(max_items[s], it.size());
             max_partial[s] = std::max(max_partial[s], it.size() * (size_t)p.WT * NSUM);
             max_tiles[s] = std::max(max_tiles[s], ts.size());
+            max_bounds[s] = std::max(max_bounds[s], bd.size());
         }
     }
     // current plan (set by the caller) may exceed candidates
     for (int s = 0; s < 2; ++s) {
         std::vector<WorkItem> it;
         std::vector<int> ts;
-        build_items(c->sp[s], W, c->WT, c->sp[s].item_exc, c->sp[s].threads, it, ts, s);
+        std::vector<int32_t> bd;
+        build_items(c->sp[s], W, c->WT, c->sp[s].item_exc, c->sp[s].threads, it, ts, s, &bd);
         max_items[s] = std::max(max_items[s], it.size());
         max_partial[s] = std::max(max_partial[s], it.size() * (size_t)c->WT * NSUM);
         max_tiles[s] = std::max(max_tiles[s], ts.size());
+        max_bounds[s] = std::max(max_bounds[s], bd.size());
     }
     const size_t Wp = (size_t)W + 64;   // room for a partial last tile of any WT (tiled buffers)
     for (int s = 0; s < 2; ++s) {
@@ -371,6 +502,7 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
         S.inv_ent = cv.take<int32_t>(sp.inv_ent.size());
         int32_t *ts = cv.take<int32_t>(max_tiles[s]);
         WorkItem *its = cv.take<WorkItem>(max_items[s]);
+        int32_t *bds = cv.take<int32_t>(std::max<size_t>(max_bounds[s], 1));
         int32_t *pu = cv.take<int32_t>(sp.U);
         S.Phi = cv.take<double>((size_t)W * sp.n * sp.no);
         S.B = cv.take<double>((size_t)W * sp.n * sp.n);
@@ -392,6 +524,8 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
             S.items = its;
             c->d_tile_slot[s] = ts;
             c->d_items[s] = its;
+            c->d_bounds[s] = bds;
+            c->bounds_cap[s] = max_bounds[s];
             c->d_perm_user[s] = pu;
             c->items_cap[s] = max_items[s];
             c->partial_cap[s] = max_partial[s];
@@ -446,11 +580,14 @@ static mde_status apply_plan(mde_ctx *c) {
         SpinDev &S = c->h.s[s];
         std::vector<WorkItem> items;
         std::vector<int> ts;
-        build_items(sp, c->W, c->WT, sp.item_exc, sp.threads, items, ts, s);
+        std::vector<int32_t> bd;
+        const ItemQueues q = build_items(sp, c->W, c->WT, sp.item_exc, sp.threads, items, ts, s, &bd);
         if (items.size() > c->items_cap[s] || items.size() * (size_t)c->WT * NSUM > c->partial_cap[s] ||
-            ts.size() > c->tileslot_cap[s])
+            ts.size() > c->tileslot_cap[s] || bd.size() > c->bounds_cap[s])
             MDE_FAIL(c, MDE_NOMEM, "plan needs more workspace than was sized (spin %d)", s);
         sp.items = items;
+        sp.bounds = bd;
+        sp.queues = q;
         sp.tile_slot = ts;
         S.WT = c->WT;
         S.WTP = (c->WT >= 8) ? c->WT + 1 : c->WT;
@@ -473,6 +610,9 @@ static mde_status apply_plan(mde_ctx *c) {
         }
         MDE_HIP(c, hipMemcpy(c->d_tile_slot[s], ts.data(), sizeof(int) * ts.size(),
                              hipMemcpyHostToDevice));
+        if (!bd.empty())
+            MDE_HIP(c, hipMemcpy(c->d_bounds[s], bd.data(), sizeof(int32_t) * bd.size(),
+                                 hipMemcpyHostToDevice));
     }
     MDE_HIP(c, hipMemcpy(c->d_inst, &c->h, sizeof(InstDev), hipMemcpyHostToDevice));
     c->R_valid[0] = c->R_valid[1] = false;
@@ -513,7 +653,7 @@ static mde_status run_values(mde_ctx *c, int s, const double *tab0 = nullptr,
         c->R_valid[s] = true;
         return MDE_OK;
     }
-    MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], (int)sp.items.size(), sp.ex_cap,
+    MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], c->d_bounds[s], sp.queues, sp.ex_cap,
                           nullptr, no_move(), DM_VALUES, c->d.precision, c->WT,
                           std::max<size_t>(sp.lds_val, 16), sp.threads, sp.grid, c->h.counter,
                           tab0, tab1));
@@ -680,6 +820,7 @@ mde_status mde_set_excitations(mde_ctx *c, int32_t spin, int32_t n_exc, const in
     for (int k = 0; k <= MAXK + 1; ++k) sp.order_start[k] = n_exc;
     for (int i = n_exc - 1; i >= 0; --i) sp.order_start[sp.orders[i]] = i;
     for (int k = MAXK; k >= 0; --k) sp.order_start[k] = std::min(sp.order_start[k], sp.order_start[k + 1]);
+    excitation_costs(sp);
     // inverted index (entry (h, p) -> (u, j, l))
     const int nm = n * sp.m;
     std::vector<int> cnt(nm + 1, 0);
@@ -911,7 +1052,7 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
     const bool prof = c->prof_on && 2 * (c->prof_used + 1) <= (int)c->prof_ev.size();
     if (prof) MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream));
     if (!sp.items.empty())
-        MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], (int)sp.items.size(), sp.ex_cap,
+        MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], c->d_bounds[s], sp.queues, sp.ex_cap,
                               nullptr, m, DM_PROPOSE, c->d.precision, c->WT, sp.lds_prop, sp.threads,
                               sp.grid, c->h.counter, nullptr, nullptr));
     if (prof) {
@@ -1271,6 +1412,7 @@ mde_status mde_group_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *by
     cv.take<InstDev>(n);
     cv.take<MoveArgs>(n);
     cv.take<WorkItem>(max_items);
+    cv.take<int32_t>(max_items * (1024 / 64 + 1));
     *bytes = cv.off + 256;
     return MDE_OK;
 }
@@ -1279,6 +1421,7 @@ static mde_status group_rebuild(mde_group *g) {
     const int n = (int)g->ctx.size();
     std::vector<WorkItem> all;
     std::vector<double> cost;
+    std::vector<int32_t> bounds;
     g->lds = 0;
     g->maxW = 0;
     g->nmax = 0;
@@ -1292,8 +1435,16 @@ static mde_status group_rebuild(mde_group *g) {
             g->ex_cap = std::max(g->ex_cap, c->sp[s].ex_cap);
             for (WorkItem it : c->sp[s].items) {
                 it.inst = i;
+                if (g->WT == 64) {
+                    double cst = 0.0;
+                    for (int u = it.u0; u < it.u1; ++u) cst += c->sp[s].ucost[u];
+                    cost.push_back(cst);
+                    it.wb = (int)bounds.size();
+                    wave_bounds(c->sp[s], it.u0, it.u1, g->threads / 64, bounds);
+                } else {
+                    cost.push_back(order_cost(it.order) * (it.u1 - it.u0) * c->WT);
+                }
                 all.push_back(it);
-                cost.push_back(order_cost(it.order) * (it.u1 - it.u0) * c->WT);
             }
         }
     }
@@ -1303,17 +1454,17 @@ static mde_status group_rebuild(mde_group *g) {
             g->lds = std::max(g->lds, det_lds(c->sp[s], c->WT, g->threads, c->d.precision, true,
                                               g->ex_cap));
         }
-    std::vector<int> idx(all.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<WorkItem> sorted;
-    sorted.reserve(all.size());
-    for (int i : idx) sorted.push_back(all[i]);
+    std::vector<WorkItem> sorted = all;
+    g->queues = queue_order(sorted, cost);
     g->n_items = (int)sorted.size();
     if (!sorted.empty())
         if (hipMemcpy(g->d_items, sorted.data(), sizeof(WorkItem) * sorted.size(),
                       hipMemcpyHostToDevice) != hipSuccess)
             MDE_GFAIL(g, MDE_DEVICE, "upload of group items failed");
+    if (!bounds.empty())
+        if (hipMemcpy(g->d_bounds, bounds.data(), sizeof(int32_t) * bounds.size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            MDE_GFAIL(g, MDE_DEVICE, "upload of group wave ranges failed");
     std::vector<InstDev> insts(n);
     for (int i = 0; i < n; ++i) insts[i] = g->ctx[i]->h;
     if (hipMemcpy(g->d_insts, insts.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice) != hipSuccess)
@@ -1356,7 +1507,14 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
     Carver cv{(char *)dev};
     g->d_insts = cv.take<InstDev>(n);
     g->d_moves = cv.take<MoveArgs>(n);
-    g->d_items = cv.take<WorkItem>(need / sizeof(WorkItem));
+    size_t max_items = 0;
+    for (int i = 0; i < n; ++i) {
+        size_t mi = 0;
+        carve(ctxs[i], ctxs[i]->W, nullptr, &mi);
+        max_items += mi;
+    }
+    g->d_items = cv.take<WorkItem>(max_items);
+    g->d_bounds = cv.take<int32_t>(max_items * (1024 / 64 + 1));
     if (hipHostMalloc((void **)&g->pinned, sizeof(MoveArgs) * n * mde_group::RING) != hipSuccess) {
         delete g;
         return MDE_NOMEM;
@@ -1450,7 +1608,7 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const
     if (launch_propose(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, g->prec, g->nmax,
                        g->mmax, g->WT, gt, split) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "propose launch");
-    if (launch_det(g->stream, g->d_insts, n, g->d_items, g->n_items, g->ex_cap, g->d_moves, none,
+    if (launch_det(g->stream, g->d_insts, n, g->d_items, g->d_bounds, g->queues, g->ex_cap, g->d_moves, none,
                    DM_PROPOSE, g->prec, g->WT, g->lds, g->threads, g->grid, g->ctx[0]->h.counter,
                    nullptr, nullptr) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "determinant launch");

@@ -11,12 +11,14 @@ constexpr int MAXM = 256;    // virtual orbitals per spin
 constexpr int MAXK = 8;      // excitation order
 constexpr int NSUM = 6;      // sums over excitations: N, q-term, x, y, z, laplacian
 
-// One unit of determinant work: excitations [u0, u1) of order `order` of
-// spin `spin` for the walkers of tile `tile` of instance `inst`.  Results go
-// to partial-sum slot `slot` of that instance and spin.
+// One unit of determinant work: excitations [u0, u1) of spin `spin` for the
+// walkers of tile `tile` of instance `inst`.  Results go to partial-sum slot
+// `slot` of that instance and spin.  64-walker tiles: the range may span
+// several orders and wave w of the block takes [bounds[wb + w],
+// bounds[wb + w + 1]); smaller tiles: one order `order`, slot-strided.
 struct WorkItem {
     int32_t inst, spin, tile, order;
-    int32_t u0, u1, slot, pad;
+    int32_t u0, u1, slot, wb;
 };
 
 // Per-spin device view of one instance.  Internal excitation order: sorted
@@ -98,6 +100,31 @@ enum DetMode { DM_PROPOSE = 0, DM_VALUES = 1 };
 // Largest excitation range of one work item (its records are staged in LDS).
 constexpr int ITEM_MAX = 1024;
 
+// The chip's workgroups are dispatched round-robin over its 8 accelerator
+// dies (XCDs), each with its own L2.  Work on walker tile t is placed on XCD
+// t % 8 by every per-move kernel, so a tile's tables stay in one L2.
+constexpr int NXCD = 8;
+
+// Work items grouped by XCD: queue x holds items [off[x], off[x+1]) (the
+// tiles t with t % 8 == x); a block drains its own XCD's queue first, then
+// helps the others.
+struct ItemQueues {
+    int32_t off[NXCD + 1];
+};
+
+// 1D grid of n_inst x T8 x split blocks (T8 = tiles rounded up to a multiple
+// of 8): block L runs on XCD L % 8 and takes (instance, tile, part) with
+// tile % 8 == L % 8.  Returns false for padding blocks.
+__device__ __forceinline__ bool tile_of_block(int split, int T8, int n_inst, int &inst, int &t,
+                                              int &part) {
+    const int L = blockIdx.x, x = L % NXCD, li = L / NXCD;
+    part = li % split;
+    const int G = (li / split) * NXCD + x;
+    inst = G / T8;
+    t = G - inst * T8;
+    return inst < n_inst;
+}
+
 // ---- launchers (stream-ordered) -------------------------------------------
 // All launchers take the device array `insts` and either a single instance
 // index range or work-item lists.
@@ -110,7 +137,8 @@ hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, in
                           const MoveArgs *d_moves, const MoveArgs &m1, int prec,
                           int nmax, int mmax, int WT, int max_tiles, int split);
 hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst,
-                      const WorkItem *items, int n_items, int ex_cap,
+                      const WorkItem *items, const int32_t *bounds, const ItemQueues &queues,
+                      int ex_cap,
                       const MoveArgs *d_moves, const MoveArgs &m1, int mode, int prec,
                       int WT, size_t lds_bytes, int threads, int grid, int32_t *counter,
                       const double *tab0, const double *tab1);
