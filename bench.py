@@ -13,8 +13,9 @@ recomputed from scratch once per sweep.  The K timed sweeps run as one HIP
 graph with all inputs resident in device memory.
 
 Metric: walker.det/s = walkers x determinants x moves / time.  The JSON line
-also carries the roofline of the determinant kernel (FP64 vector ALU), the
-CPU oracle timed on a bounded sample of the same workload, and the other
+also carries the roofline of the determinant kernel (bound by HBM: it streams
+every walker's CI weights once per move; its FP64 vector-ALU figure beside),
+the CPU oracle timed on a bounded sample of the same workload, and the other
 precision forms.
 """
 from __future__ import annotations
@@ -49,6 +50,16 @@ def det_flops(k: int) -> int:
 def flops_per_launch(exc, W: int) -> float:
     orders = exc.orders()
     return float(W) * sum(det_flops(int(k)) for k in orders if k > 0)
+
+
+def bytes_per_launch(exc, W: int, n: int, m: int, precision: str) -> float:
+    """Algorithmic HBM bytes of one determinant-kernel launch: each walker's CI
+    weight C_u of every excitation of the moving spin (8 B, read once), the
+    walker's tables once (FP64 form: T [n*m], q and w^a [5m], c [n]; mixed
+    forms: FP32 T' [n*m], g^a [4m], c' [n]) and its five output sums."""
+    U = int((exc.orders() > 0).sum())
+    tab = 8 * (n * m + 5 * m + n) if precision == "fp64" else 4 * (n * m + 4 * m + n)
+    return float(W) * (8 * U + tab + 5 * 8)
 
 
 def log(*a):
@@ -143,10 +154,14 @@ def run_form(wl, precision, steps, warmup, autotune=True):
     ms_step = ms_total / steps
     wdets = W * s.n_det * n_tot
     fl = np.mean([flops_per_launch(s.exc[ctx.spin_of(m[0])], W) for m in moves])
+    by = np.mean([bytes_per_launch(s.exc[sp], W, s.n_elec[sp], s.n_orb[sp] - s.n_elec[sp], precision)
+                  for sp in (ctx.spin_of(m[0]) for m in moves)])
     det_avg_s = det_ms / max(det_n, 1) / 1e3
     return dict(precision=precision, ms_per_step=ms_step, value=wdets / (ms_step / 1e3),
                 ms_per_step_eager=ms_eager / steps,
                 det_launches=det_n, det_avg_us=det_avg_s * 1e6, det_flops_per_launch=fl,
+                det_bytes_per_launch=by,
+                det_gbs=by / det_avg_s / 1e9 if det_n else None,
                 det_tflops=fl / det_avg_s / 1e12 if det_n else None, plan=plan,
                 status_bits=int(np.bitwise_or.reduce(st.ravel())) if st.size else 0)
 
@@ -205,11 +220,12 @@ def main():
     for f in [x for x in args.forms.split(",") if x]:
         r = run_form(wl, f, args.steps, args.warmup, autotune=not args.no_autotune)
         log(f"{f}: {r['ms_per_step']:.3f} ms/sweep  {r['value']:.3e} walker.det/s  "
-            f"det kernel {r['det_avg_us']:.1f} us ({r['det_tflops']:.2f} TFLOP/s) plan {r['plan'][0]}")
+            f"det kernel {r['det_avg_us']:.1f} us ({r['det_gbs']:.0f} GB/s, {r['det_tflops']:.2f} TFLOP/s) "
+            f"plan {r['plan'][0]}")
         forms[f] = r
     head = forms.get("fp64") or next(iter(forms.values()))
     cpu = None if args.no_cpu else cpu_baseline(wl)
-    achieved = head["det_tflops"]
+    achieved = head["det_gbs"]
     traffic = None
     out = {
         "metric": "excited-det ratios/s (walker.det, +grad/lap) mixed/batched vs plain FP64",
@@ -229,14 +245,17 @@ def main():
                                "step = one sweep of 10 single-electron moves, 50% accepted",
                    "walkers": wl.walkers.W, "n_det": wl.system.n_det,
                    "moves_per_step": sum(wl.system.n_elec), "precision": head["precision"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic, "kernel": "k_det<double, propose>",
                      "launch_us": head["det_avg_us"],
-                     "flops_per_launch": head["det_flops_per_launch"]},
+                     "bytes_per_launch": head["det_bytes_per_launch"],
+                     "alu": {"achieved": head["det_tflops"], "peak": PEAK_FP64_VECTOR_TFLOPS,
+                             "unit": "TFLOP/s", "frac": head["det_tflops"] / PEAK_FP64_VECTOR_TFLOPS,
+                             "flops_per_launch": head["det_flops_per_launch"]}},
         "cpu_baseline": cpu,
         "forms": {k: {kk: v[kk] for kk in ("value", "ms_per_step", "ms_per_step_eager", "det_avg_us",
-                                           "det_tflops", "status_bits", "plan")}
+                                           "det_gbs", "det_tflops", "status_bits", "plan")}
                   for k, v in forms.items()},
     }
     print(json.dumps(out))
