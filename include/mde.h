@@ -65,11 +65,11 @@ typedef enum {
                              Sherman-Morrison table update, the small
                              determinants, LU, denominators and CI sums are
                              computed in FP64                                 */
-    MDE_MIXED_GEMM = 2    /* as MDE_MIXED, but every accepted move rebuilds
-                             the table with one FP32 MFMA GEMM
-                             T = A^-1 Phi_V (Algorithm 1 step 3) instead of
-                             the rank-one update; its error grows with the
-                             condition number of the reference matrix       */
+    MDE_MIXED_GEMM = 2    /* as MDE_MIXED, but every proposal rebuilds the
+                             table with one FP32 MFMA GEMM T' = A'^-1 Phi'_V
+                             (Algorithm 1 step 3) instead of the rank-one
+                             update; its error grows with the condition
+                             number of the reference matrix                 */
 } mde_precision;
 
 /* per-walker status bits */
