@@ -689,15 +689,20 @@ hipError_t launch_coef_gather(hipStream_t st, const InstDev *d_inst, const InstD
 // partial sums that k_pc_fix adds in piece order.
 template <int WT>
 __global__ void __launch_bounds__(256)
-k_precontract(const InstDev *__restrict__ insts, int spin) {
+k_precontract(const InstDev *__restrict__ insts, int spin, int ublocks) {
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[spin];
     const SpinDev &O = I.s[1 - spin];
     constexpr int per_block = 256 / WT;
     const int wl = threadIdx.x % WT;
-    int unit = blockIdx.y * per_block + threadIdx.x / WT;
+    // walker tile t runs on die t % 8, all unit blocks of a tile in a row:
+    // the other spin's ratios of the tile stay in that die's L2 while its
+    // CI terms gather them
+    const int L = blockIdx.x, x = L % NXCD, li = L / NXCD;
+    const int t = (li / ublocks) * NXCD + x, ub = li % ublocks;
+    if (t >= S.n_tiles) return;
+    int unit = ub * per_block + threadIdx.x / WT;
     if (WT == 64) unit = __builtin_amdgcn_readfirstlane(unit);
-    const int t = blockIdx.x;
     if (unit >= S.n_chunks + S.n_pieces) return;
     const auto seg = MDE_G(int32_t, S.ci_seg);
     const auto oth = MDE_G(int32_t, S.ci_other);
@@ -726,6 +731,56 @@ k_precontract(const InstDev *__restrict__ insts, int spin) {
     }
     const auto Cw = MDE_GW(double, out);
     double s = 0.0;
+    if (WT == 64) {
+        // One unit per wave.  The unit's terms (other-spin excitation and
+        // coefficient, at most 2 x 64) and segment ends are loaded into the
+        // lanes with one vector load each and read back by lane index, so no
+        // scalar load sits on the chain; the gathers go out 16 at a time.
+        const int lane = threadIdx.x & 63;
+        const int nk = k1 - k0;
+        const int o_a = lane < nk ? oth[k0 + lane] : 0;
+        const int o_b = 64 + lane < nk ? oth[k0 + 64 + lane] : 0;
+        const double c_a = lane < nk ? cf[k0 + lane] : 0.0;
+        const double c_b = 64 + lane < nk ? cf[k0 + 64 + lane] : 0.0;
+        // ends of the chunk's excitations (pieces: one segment ending at k1)
+        const bool chunk = ostride != 0;
+        const int ne = u1 - u;
+        const int e_a = chunk ? (lane < ne ? seg[u + 1 + lane] : k1) : k1;
+        const int e_b = chunk ? (64 + lane < ne ? seg[u + 65 + lane] : k1) : k1;
+        auto lane_i = [](int v, int i) { return __builtin_amdgcn_readlane(v, i); };
+        auto lane_d = [](double v, int i) {
+            const long long b = __double_as_longlong(v);
+            const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), i);
+            const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+            return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        };
+        int e = 0;   // index of the current excitation within the unit
+        int kend_l = lane_i(e_a, 0);
+        for (int tb = 0; tb < nk; tb += 16) {
+            double r[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int kk = tb + i;
+                const int oi = kk < 64 ? lane_i(o_a, kk & 63) : lane_i(o_b, kk & 63);
+                r[i] = kk < nk ? Ro[(size_t)oi * WT] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int kk = tb + i;
+                if (kk < nk) {
+                    while (k0 + kk >= kend_l) {
+                        Cw[(size_t)(u + e) * ostride] = s;
+                        s = 0.0;
+                        ++e;
+                        kend_l = e < 64 ? lane_i(e_a, e) : lane_i(e_b, e - 64);
+                    }
+                    const double c = kk < 64 ? lane_d(c_a, kk & 63) : lane_d(c_b, kk & 63);
+                    s = fma(c, r[i], s);
+                }
+            }
+        }
+        u += e;
+    } else
     for (int k = k0; k < k1; k += 8) {
         int o[8];
         double c[8], r[8];
@@ -777,11 +832,12 @@ hipError_t launch_precontract(hipStream_t st, const InstDev *d_inst, const InstD
     const SpinDev &S = h.s[spin];
     const int per_block = 256 / S.WT;
     const int units = S.n_chunks + S.n_pieces;
-    // tiles fastest: consecutive blocks work on different walker tiles
-    dim3 grid(S.n_tiles, (units + per_block - 1) / per_block);
+    const int ublocks = (units + per_block - 1) / per_block;
+    const int T8 = (S.n_tiles + NXCD - 1) / NXCD * NXCD;
+    dim3 grid(T8 * ublocks);
 #define MDE_PC(X)                                                                       \
     case X:                                                                             \
-        hipLaunchKernelGGL(k_precontract<X>, grid, dim3(256), 0, st, d_inst, spin);     \
+        hipLaunchKernelGGL(k_precontract<X>, grid, dim3(256), 0, st, d_inst, spin, ublocks); \
         break;
     switch (S.WT) {
         MDE_PC(1) MDE_PC(2) MDE_PC(4) MDE_PC(8) MDE_PC(16) MDE_PC(32) MDE_PC(64)

@@ -899,7 +899,9 @@ mde_status mde_set_ci(mde_ctx *c, int64_t n_det, const double *coef, const int32
                 continue;
             }
             acc += len;
-            if (acc >= PIECE) {
+            // a chunk holds at most 127 terms and 64 excitations (one wave
+            // keeps them in its lanes)
+            if (acc >= PIECE || u + 1 - cur >= 64) {
                 starts.push_back(cur);
                 ends.push_back(u + 1);
                 cur = u + 1;
