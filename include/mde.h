@@ -208,6 +208,23 @@ mde_status mde_set_plan(mde_ctx *ctx, int32_t spin, int32_t walker_tile,
 mde_status mde_get_plan(const mde_ctx *ctx, int32_t spin, int32_t *walker_tile,
                         int32_t *item_exc, int32_t *threads);
 
+/* Host-only inspection of the determinant kernel's work decomposition for
+ * one spin under a plan (walker tile, item size, threads) and W walkers; no
+ * device call, usable before binding.  items: up to items_cap records of 10
+ * int32 each (instance, spin, tile, order, u0, u1, slot, wb, d0, d1) --
+ * excitations are in the library's internal order (ascending order, holes,
+ * particles; 0 is the reference; orders 1 and 2 may be filled dense);
+ * [u0, u1) is the item's range with staged records and [d0, d1) its share of
+ * the dense block; wb indexes `ranges`.  ranges: up to ranges_cap int32, the
+ * per-wave (first, end) pairs of 64-walker items (threads / 64 pairs per
+ * item).  layout[0..3] = (internal excitation count, first and end of the
+ * dense block, its order mask).  *n_items and *n_ranges receive the full
+ * counts; MDE_NOMEM when a capacity is too small. */
+mde_status mde_debug_items(const mde_ctx *ctx, int32_t spin, int32_t W, int32_t walker_tile,
+                           int32_t item_exc, int32_t threads, int32_t *items, int32_t items_cap,
+                           int32_t *n_items, int32_t *ranges, int32_t ranges_cap,
+                           int32_t *n_ranges, int32_t *layout);
+
 /* Time candidate plans on this context's current state (after mde_init) with
  * proposals of electron 0 and electron n_up (new_orb_up/new_orb_dn: device
  * blocks [W][5][n_orb]); keep the fastest per spin.  If cache_path is not

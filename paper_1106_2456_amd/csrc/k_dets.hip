@@ -77,10 +77,13 @@ __device__ __forceinline__ double det_one(const uint4 &ex, const TT *__restrict_
     return dd;
 }
 
-template <typename TT, int MODE>
+// With WS the e-terms go to the lane's per-particle weights Wl[p * 64]
+// instead of being gathered (64-walker tiles).
+template <typename TT, int MODE, bool WS = false>
 __device__ double det_one_generic(int k, const uint4 &ex, const TT *__restrict__ tabs,
                                   const TT *__restrict__ gs, const TT *__restrict__ cs, int m,
-                                  int WTP, int wl, double Cu, double acc[NSUM]) {
+                                  int WTP, int wl, double Cu, double acc[NSUM],
+                                  double *Wl = nullptr) {
     int h[MAXK], p[MAXK];
     for (int j = 0; j < k; ++j) {
         h[j] = exc_byte(ex, j);
@@ -96,6 +99,10 @@ __device__ double det_one_generic(int k, const uint4 &ex, const TT *__restrict__
     constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
     for (int j = 0; j < k; ++j) {
         const double wy = Cu * y[j];
+        if (WS) {
+            atomicAdd(Wl + p[j] * 64, wy);
+            continue;
+        }
         for (int b = 0; b < NE; ++b)
             acc[1 + b] = fma((double)gs[(p[j] * NE + b) * WTP + wl], wy, acc[1 + b]);
     }
@@ -135,6 +142,10 @@ __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
 // The lanes of a wave are 64 walkers and every index is wave-uniform: the
 // records (staged in LDS with the tables) are broadcast to the wave and all
 // control flow is scalar.
+// The e-terms sum_u C_u sum_j e^b[p_j] y_j are linear in e, so each lane
+// collects per-particle weights W[p] += C_u y_j (one LDS add, in program
+// order, into its wave's own rows: no gathers of e^b) and the block
+// contracts W with e^b once per work item.
 // Excitations are sorted by holes, then particles, so consecutive
 // excitations of one order share their holes h_0..h_{K-1} and, often, their
 // first K-1 particles (the prefix).  Within such a run only the last column
@@ -142,27 +153,22 @@ __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
 //   det S = u . b,                 u = cofactors of the last column
 //   y_j   = v_j . b   (j < K-1),   v_j = the same with column j -> c'[h]
 //   y_{K-1} = u . c'[h]            (constant over the run)
-// so per excitation the wave gathers K table entries and the NE values e^b[q],
-// and the run accumulates
-//   Nrun += C det S,  Yrun_j += C y_j,  Zrun^b += C e^b[q];
-// on closing the run
-//   acc[0] += Nrun,  acc[1+b] += y_{K-1} Zrun^b + sum_j e^b[p_j] Yrun_j.
-
-
+// so per excitation the wave gathers K table entries, adds C y_{K-1} to
+// W[q], and the run accumulates Nrun += C det S, Yrun_j += C y_j; on
+// closing the run acc[0] += Nrun and W[p_j] += Yrun_j.
 
 __device__ __forceinline__ int byte_of(uint32_t w, int i) { return (int)((w >> (8 * i)) & 0xffu); }
 
 template <int K, typename TT, int MODE>
 __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, int j1,
                                            const uint32_t *exw, int u0,
-                                           const TT *__restrict__ tabs, const TT *__restrict__ gs,
-                                           const TT *__restrict__ cs, int wl, double acc[NSUM]) {
+                                           const TT *__restrict__ tabs, const TT *__restrict__ cs,
+                                           int wl, double *Wl, double acc[NSUM]) {
     constexpr int KP = K - 1;                  // prefix length
     constexpr int KQ = KP > 0 ? KP : 1;
     constexpr uint32_t PMASK = KP == 0 ? 0u : (KP >= 4 ? 0xffffffffu : ((1u << (8 * KP)) - 1u));
-    constexpr int WTP = 65;
+    constexpr int WTP = lds_row_stride(64);
     constexpr int D = 4;                       // CI weights loaded ahead
-    constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
     if (j0 >= j1) return;
     const int m = S.m;
     const size_t cb0 = (size_t)tile * S.U * 64 + wl;
@@ -172,7 +178,7 @@ __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, i
     uint32_t hx = 0, pz = 0;
     int rb[K];
     double c[K], u[K], v[KQ][K];
-    double ylast = 0.0, Nrun = 0.0, Yrun[KQ], Zrun[NE];
+    double ylast = 0.0, Nrun = 0.0, Yrun[KQ];
 #pragma unroll
     for (int r = 0; r < K; ++r) { rb[r] = 0; c[r] = 0.0; u[r] = 0.0; }
 #pragma unroll
@@ -181,19 +187,11 @@ __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, i
 #pragma unroll
         for (int r = 0; r < K; ++r) v[j][r] = 0.0;
     }
-#pragma unroll
-    for (int b = 0; b < NE; ++b) Zrun[b] = 0.0;
 
     auto close_run = [&]() {
         acc[0] += Nrun;
 #pragma unroll
-        for (int b = 0; b < NE; ++b) {
-            double s = ylast * Zrun[b];
-#pragma unroll
-            for (int j = 0; j < KP; ++j)
-                s = fma((double)gs[(byte_of(pz, j) * NE + b) * WTP + wl], Yrun[j], s);
-            acc[1 + b] += s;
-        }
+        for (int j = 0; j < KP; ++j) atomicAdd(Wl + byte_of(pz, j) * 64, Yrun[j]);
     };
 
     auto step = [&](const uint32_t hw, const uint32_t pw, double Cu, int j) {
@@ -222,8 +220,6 @@ __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, i
                 Nrun = 0.0;
 #pragma unroll
                 for (int i = 0; i < KQ; ++i) Yrun[i] = 0.0;
-#pragma unroll
-                for (int b = 0; b < NE; ++b) Zrun[b] = 0.0;
             }
             else
                 last_cofactors<K, double>(P, u);
@@ -248,8 +244,7 @@ __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, i
             for (int r = 0; r < K; ++r) y = fma(v[i][r], b[r], y);
             Yrun[i] = fma(Cu, y, Yrun[i]);
         }
-#pragma unroll
-        for (int b = 0; b < NE; ++b) Zrun[b] = fma(Cu, (double)gs[(q * NE + b) * WTP + wl], Zrun[b]);
+        atomicAdd(Wl + q * 64, Cu * ylast);
     };
 
     // records and CI weights of the next group are loaded while the current
@@ -290,19 +285,19 @@ __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, i
 }
 
 // Orders whose prefix runs are short (triples and quadruples rarely share
-// their first K-1 particles): every excitation gathers its K x K block, c[h]
-// and e^b[p_j], in groups of D with no branches between them, so the LDS
-// reads of one excitation overlap the arithmetic of the previous one.  Past
-// the end of the range the group repeats the last excitation with weight 0
-// (and, for values, rewrites the same ratio).
+// their first K-1 particles): every excitation gathers its K x K block, in
+// groups of D with no branches between them but the reload of c[h] when the
+// hole set changes (excitations are sorted by holes), so the LDS reads of
+// one excitation overlap the arithmetic of the previous one.  Past the end
+// of the range the group repeats the last excitation with weight 0 (and,
+// for values, rewrites the same ratio).
 template <int K, typename TT, int MODE>
 __device__ __forceinline__ void det_direct64(const SpinDev &S, int tile, int j0, int j1,
                                              const uint32_t *exw, int u0,
-                                             const TT *__restrict__ tabs, const TT *__restrict__ gs,
-                                             const TT *__restrict__ cs, int wl, double acc[NSUM]) {
-    constexpr int WTP = 65;
+                                             const TT *__restrict__ tabs, const TT *__restrict__ cs,
+                                             int wl, double *Wl, double acc[NSUM]) {
+    constexpr int WTP = lds_row_stride(64);
     constexpr int D = 4;
-    constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
     if (j0 >= j1) return;
     const int m = S.m;
     const size_t cb0 = (size_t)tile * S.U * 64 + wl;
@@ -310,6 +305,10 @@ __device__ __forceinline__ void det_direct64(const SpinDev &S, int tile, int j0,
     const auto Rg = MDE_GW(double, S.R) + cb0;
     uint32_t hA[D], pA[D], hB[D], pB[D];
     double cA[D], cB[D];
+    uint32_t hx = 0xffffffffu;      // hole set of the cached c[h]
+    double c[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) c[r] = 0.0;
     auto fetch = [&](int jb, uint32_t (&h)[D], uint32_t (&pp)[D], double (&cv)[D]) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -324,39 +323,37 @@ __device__ __forceinline__ void det_direct64(const SpinDev &S, int tile, int j0,
                          const double (&cb)[D]) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            int h[K], hm[K], p[K];
+            int hm[K], p[K];
             const uint32_t hw = __builtin_amdgcn_readfirstlane(hc[i]);
             const uint32_t pw = __builtin_amdgcn_readfirstlane(pc[i]);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                h[r] = byte_of(hw, r);
-                hm[r] = h[r] * m;
+                hm[r] = byte_of(hw, r) * m;
                 p[r] = byte_of(pw, r);
             }
-            double col[K][K], c[K], y[K];
+            double col[K][K], y[K];
 #pragma unroll
             for (int jc = 0; jc < K; ++jc)
 #pragma unroll
                 for (int r = 0; r < K; ++r) col[jc][r] = (double)tabs[(hm[r] + p[jc]) * WTP + wl];
             if (MODE == DM_VALUES) {
+                double z[K];
 #pragma unroll
-                for (int r = 0; r < K; ++r) c[r] = 0.0;
-                const double dd = SmallDet<K, double>::run(col, c, y);
+                for (int r = 0; r < K; ++r) z[r] = 0.0;
+                const double dd = SmallDet<K, double>::run(col, z, y);
                 Rg[(size_t)min(j + i, j1 - 1) * 64] = dd;
                 continue;
             }
+            if (hw != hx) {
+                hx = hw;
 #pragma unroll
-            for (int r = 0; r < K; ++r) c[r] = (double)cs[h[r] * WTP + wl];
+                for (int r = 0; r < K; ++r) c[r] = (double)cs[byte_of(hw, r) * WTP + wl];
+            }
             const double dd = SmallDet<K, double>::run(col, c, y);
             const double Cu = (j + i < j1) ? cb[i] : 0.0;
             acc[0] = fma(Cu, dd, acc[0]);
 #pragma unroll
-            for (int jc = 0; jc < K; ++jc) {
-                const double wy = Cu * y[jc];
-#pragma unroll
-                for (int b = 0; b < NE; ++b)
-                    acc[1 + b] = fma((double)gs[(p[jc] * NE + b) * WTP + wl], wy, acc[1 + b]);
-            }
+            for (int jc = 0; jc < K; ++jc) atomicAdd(Wl + p[jc] * 64, Cu * y[jc]);
         }
     };
     fetch(j0, hA, pA, cA);
@@ -374,8 +371,7 @@ __device__ __forceinline__ void det_direct64(const SpinDev &S, int tile, int j0,
 template <typename TT, int MODE>
 __device__ void det_generic64(const SpinDev &S, int tile, int k, int j0, int j1,
                               const uint32_t *exw, int u0, const TT *__restrict__ tabs,
-                              const TT *__restrict__ gs, const TT *__restrict__ cs, int wl,
-                              double acc[NSUM]) {
+                              const TT *__restrict__ cs, int wl, double *Wl, double acc[NSUM]) {
     const size_t cb0 = (size_t)tile * S.U * 64 + wl;
     const auto Cg = MDE_G(double, S.C) + cb0;
     const auto Rg = MDE_GW(double, S.R) + cb0;
@@ -387,7 +383,8 @@ __device__ void det_generic64(const SpinDev &S, int tile, int k, int j0, int j1,
         ex.z = __builtin_amdgcn_readfirstlane(ex.z);
         ex.w = __builtin_amdgcn_readfirstlane(ex.w);
         const double Cu = MODE == DM_PROPOSE ? Cg[(size_t)j * 64] : 0.0;
-        const double R = det_one_generic<TT, MODE>(k, ex, tabs, gs, cs, S.m, 65, wl, Cu, acc);
+        const double R = det_one_generic<TT, MODE, true>(k, ex, tabs, nullptr, cs, S.m,
+                                                         lds_row_stride(64), wl, Cu, acc, Wl);
         if (MODE == DM_VALUES) Rg[(size_t)j * 64] = R;
     }
 }
@@ -413,8 +410,364 @@ __device__ __forceinline__ void stage_rows(TT *__restrict__ dst, const ST __attr
     for (; idx < count; idx += nthr) dst[(idx / WT) * WTP + idx % WT] = (TT)src[idx];
 }
 
+// ---------------------------------------------------------------------------
+// Dense blocks of orders 1 and 2 (every excitation of the order present, in
+// canonical order: hole sets ascending, particles ascending inside a hole
+// set; m == M).  A hole set's table rows are held in registers and its CI
+// weights are streamed in order, so no record, gather or per-excitation
+// e-row is needed.  For a double with rows a = Tab[h0][.], b = Tab[h1][.],
+// c0 = c[h0], c1 = c[h1] and particles p < q:
+//   det S = a_p b_q - a_q b_p,   y = adj(S) (c0, c1) = (z_q, -z_p),
+//   z = c0 b - c1 a,
+// so with S1_p = sum_{q>p} C b_q and S2_p = sum_{q>p} C a_q (one row of
+// the block):
+//   sum C det S                  = sum_p (a_p S1_p - b_p S2_p)
+//   sum C (e_p y_0 + e_q y_1)    = sum_p e_p (c0 S1_p - c1 S2_p)
+//                                  - sum_q e_q sum_{p<q} C z_p.
+// A single h -> q has det = a_q and y = c[h].  The e-terms are collected in
+// registers as per-particle weights Wt[q] and added to the lane's LDS
+// weights once per range.  Per excitation: one CI weight and three FMAs.
+// ---------------------------------------------------------------------------
+
+// loads of CI weights in flight: a divisor of the block length (at most
+// CAP), so the ring slot of an excitation is the same in every hole set
+template <int NB, int CAP>
+__host__ __device__ constexpr int dense_pd() {
+    int d = NB < CAP ? NB : CAP;
+    while (NB % d) --d;
+    return d;
+}
+
+// One unit [S0, S0 + UNIT) of the hole pair with rows a = Tab[h0][.],
+// b = Tab[h1][.]; `base` is the pair's first excitation.  The ring and the
+// lane's weights carry over between units.
+template <int M, int S0, typename TT, int MODE>
+__device__ __forceinline__ void dense2_unit(const double (&a)[M], const double (&b)[M], double c0,
+                                            double c1, int base, int j1,
+                                            const double __attribute__((address_space(1))) *Cg,
+                                            double __attribute__((address_space(1))) *Rg,
+                                            double (&cb)[Dense2Shape<M>::PD], double *Wl,
+                                            double &s0) {
+    constexpr int PD = Dense2Shape<M>::PD, S1E = S0 + Dense2Shape<M>::UNIT;
+    int sl = 0;
+#pragma unroll
+    for (int p = 0; p < M - 1; ++p) {
+        const int rs = sl, re = sl + (M - 1 - p);   // the row's slots
+        sl = re;
+        if (re <= S0 || rs >= S1E) continue;
+        double S1 = 0.0, S2 = 0.0, zp = 0.0;
+        if (MODE == DM_PROPOSE) zp = fma(c0, b[p], -c1 * a[p]);
+#pragma unroll
+        for (int q = p + 1; q < M; ++q) {
+            const int x = rs + (q - p - 1);
+            if (x < S0 || x >= S1E) continue;
+            if (MODE == DM_VALUES) {
+                Rg[(size_t)(base + x) * 64] = fma(a[p], b[q], -a[q] * b[p]);
+                continue;
+            }
+            const double C = cb[x % PD];
+            cb[x % PD] = Cg[(size_t)min(base + x + PD, j1 - 1) * 64];
+            __asm__ volatile("" ::: "memory");
+            S1 = fma(C, b[q], S1);
+            S2 = fma(C, a[q], S2);
+            atomicAdd(Wl + q * 64, -C * zp);
+        }
+        if (MODE == DM_PROPOSE) {
+            s0 = fma(a[p], S1, fma(-b[p], S2, s0));
+            atomicAdd(Wl + p * 64, fma(c0, S1, -c1 * S2));
+        }
+    }
+}
+
+// all units of a pair in one straight-line body; units outside [g0, g1) are skipped
+template <int M, int G, typename TT, int MODE>
+__device__ __forceinline__ void dense2_pair(const double (&a)[M], const double (&b)[M], double c0,
+                                            double c1, int base, int j1, int g0, int g1,
+                                            const double __attribute__((address_space(1))) *Cg,
+                                            double __attribute__((address_space(1))) *Rg,
+                                            double (&cb)[Dense2Shape<M>::PD], double *Wl,
+                                            double &s0) {
+    if constexpr (G < Dense2Shape<M>::G) {
+        if (G >= g0 && G < g1)
+            dense2_unit<M, G * Dense2Shape<M>::UNIT, TT, MODE>(a, b, c0, c1, base, j1, Cg, Rg, cb,
+                                                               Wl, s0);
+        dense2_pair<M, G + 1, TT, MODE>(a, b, c0, c1, base, j1, g0, g1, Cg, Rg, cb, Wl, s0);
+    }
+}
+
+template <int M, typename TT, int MODE>
+__device__ __forceinline__ void det_dense(const SpinDev &S, int k, int tile, int j0, int j1,
+                                          const TT *tabs, const TT *__restrict__ cs,
+                                          int wl, double *Wl, double acc[NSUM]) {
+    constexpr int WTP = lds_row_stride(64);
+    if (j0 >= j1) return;
+    const int n = S.n;
+    const size_t cb0 = (size_t)tile * S.U * 64 + wl;
+    const auto Cg = MDE_G(double, S.C) + cb0;
+    const auto Rg = MDE_GW(double, S.R) + cb0;
+    const int a0 = S.order_start[k];
+    double Wt[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) Wt[q] = 0.0;
+    if (k == 1) {
+        constexpr int PD = dense_pd<M, 24>();
+        double cb[PD];
+        if (MODE == DM_PROPOSE) {
+#pragma unroll
+            for (int i = 0; i < PD; ++i) cb[i] = Cg[(size_t)min(j0 + i, j1 - 1) * 64];
+        }
+        for (int base = j0; base < j1; base += M) {
+            const int h = (base - a0) / M;
+            double a[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) a[q] = (double)tabs[(h * M + q) * WTP + wl];
+            if (MODE == DM_VALUES) {
+#pragma unroll
+                for (int q = 0; q < M; ++q) Rg[(size_t)(base + q) * 64] = a[q];
+                continue;
+            }
+            const double ch = (double)cs[h * WTP + wl];
+            double s0 = 0.0;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                const double C = cb[q % PD];
+                cb[q % PD] = Cg[(size_t)min(base + q + PD, j1 - 1) * 64];
+                __asm__ volatile("" ::: "memory");
+                s0 = fma(C, a[q], s0);
+                Wt[q] = fma(C, ch, Wt[q]);
+            }
+            acc[0] += s0;
+        }
+    } else {
+        using SH = Dense2Shape<M>;
+        constexpr int PD = SH::PD, NP = SH::NP, UNIT = SH::UNIT;
+        double cb[PD];
+        if (MODE == DM_PROPOSE) {
+#pragma unroll
+            for (int i = 0; i < PD; ++i) cb[i] = Cg[(size_t)min(j0 + i, j1 - 1) * 64];
+        }
+        // hole pair and unit of the first excitation of the range
+        int hp = (j0 - a0) / NP, h0 = 0;
+        int g = (j0 - a0 - hp * NP) / UNIT;
+        while (hp >= n - 1 - h0) { hp -= n - 1 - h0; ++h0; }
+        int h1 = h0 + 1 + hp;
+        double s0 = 0.0;
+        for (int u = j0; u < j1;) {
+            const int base = u - g * UNIT;
+            const int g1 = min(SH::G, g + (j1 - u) / UNIT);
+            double a[M], b[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                a[q] = (double)tabs[(h0 * M + q) * WTP + wl];
+                b[q] = (double)tabs[(h1 * M + q) * WTP + wl];
+            }
+            double c0 = 0.0, c1 = 0.0;
+            if (MODE == DM_PROPOSE) {
+                c0 = (double)cs[h0 * WTP + wl];
+                c1 = (double)cs[h1 * WTP + wl];
+            }
+            dense2_pair<M, 0, TT, MODE>(a, b, c0, c1, base, j1, g, g1, Cg, Rg, cb, Wl, s0);
+            u += (g1 - g) * UNIT;
+            g = 0;
+            if (++h1 == n) { ++h0; h1 = h0 + 1; }
+        }
+        acc[0] += s0;
+    }
+    if (MODE == DM_PROPOSE && k == 1) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) atomicAdd(Wl + q * 64, Wt[q]);
+    }
+}
+
+template <typename TT, int MODE>
+__device__ __forceinline__ void det_dense_m(const SpinDev &S, int k, int tile, int j0, int j1,
+                                            const TT *tabs, const TT *__restrict__ cs,
+                                            int wl, double *Wl, double acc[NSUM]) {
+    switch (S.m) {
+        case 8: det_dense<8, TT, MODE>(S, k, tile, j0, j1, tabs, cs, wl, Wl, acc); break;
+        case 12: det_dense<12, TT, MODE>(S, k, tile, j0, j1, tabs, cs, wl, Wl, acc); break;
+        case 16: det_dense<16, TT, MODE>(S, k, tile, j0, j1, tabs, cs, wl, Wl, acc); break;
+        case 20: det_dense<20, TT, MODE>(S, k, tile, j0, j1, tabs, cs, wl, Wl, acc); break;
+        case 24: det_dense<24, TT, MODE>(S, k, tile, j0, j1, tabs, cs, wl, Wl, acc); break;
+        default: break;
+    }
+}
+
+// Copy of up to four segments (16-byte units) into LDS with all loads of a
+// thread issued before its LDS writes: the records before and after the
+// dense block, the table and c of a 64-walker tile arrive in one round trip.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+struct StageSeg {
+    const u32x4_t __attribute__((address_space(1))) *src;
+    u32x4_t *dst;
+    int n;
+};
+__device__ __forceinline__ void stage_segs(const StageSeg &s0, const StageSeg &s1,
+                                           const StageSeg &s2, const StageSeg &s3, int tid,
+                                           int nthr) {
+    constexpr int U = 16;
+    const int c1 = s0.n, c2 = c1 + s1.n, c3 = c2 + s2.n, tot = c3 + s3.n;
+    for (int base = tid; base < tot; base += U * nthr) {
+        u32x4_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * nthr;
+            if (i < tot) {
+                const auto sp = i < c1 ? s0.src + i
+                                       : i < c2 ? s1.src + (i - c1)
+                                                : i < c3 ? s2.src + (i - c2) : s3.src + (i - c3);
+                v[u] = *sp;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * nthr;
+            if (i < tot) {
+                u32x4_t *dp = i < c1 ? s0.dst + i
+                                     : i < c2 ? s1.dst + (i - c1)
+                                              : i < c3 ? s2.dst + (i - c2) : s3.dst + (i - c3);
+                *dp = v[u];
+            }
+        }
+    }
+}
+
+// One work item on a 64-walker tile.  LDS: [records][Tab n*m rows][c n rows]
+// [W: per wave, m rows of 64 FP64 particle weights].  Each wave evaluates
+// its range (dense units or a piece of the sparse range) order by order;
+// the e-terms are collected in W.
+// At the end the block sums W over the waves, contracts it with e^b (the
+// values are loaded before the barrier) and writes the item's NSUM sums per
+// walker in a fixed order.
+template <typename TT, int MODE>
+__device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, const SpinDev &S,
+                                       uint4 *exl, unsigned char *tab_raw,
+                                       const int32_t *__restrict__ bounds, int tid, int nthr,
+                                       const double *tab0, const double *tab1) {
+    constexpr int WT = 64, WTP = lds_row_stride(64);
+    constexpr int NE = sizeof(TT) == 8 ? 5 : 4;
+    constexpr int QPT = 3;        // e-values prefetched per thread (particles wave, wave+nw, ..)
+    const int n = S.n, m = S.m, W = I.W, nm = n * m;
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    TT *tabs = reinterpret_cast<TT *>(tab_raw);
+    TT *cs = tabs + nm * WTP;
+    double *Wall = reinterpret_cast<double *>(cs + n * WTP);
+    double *Wl = Wall + (size_t)wave * m * 64 + lane;
+    uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
+    // records of the item's sparse range [u0, u1) (the dense block needs
+    // none): record u at exw[4 * (u - u0)]
+    using G4 = const u32x4_t __attribute__((address_space(1))) *;
+    const G4 exg = (G4)(S.ex);
+    u32x4_t *exd = reinterpret_cast<u32x4_t *>(exl);
+    StageSeg r0{exg + it.u0, exd, it.u1 - it.u0};
+    StageSeg r1{exg, exd, 0};
+    const int w0 = it.tile * WT;
+    const size_t tn = (size_t)it.tile * nm * WT, tc = (size_t)it.tile * n * WT;
+    const double *tabd = it.spin == 0 ? tab0 : tab1;
+    if (MODE == DM_PROPOSE) {
+        const void *tsrc = sizeof(TT) == 8 ? (const void *)S.T : (const void *)I.Tp32;
+        const void *csrc = sizeof(TT) == 8 ? (const void *)I.cc : (const void *)I.cc32;
+        StageSeg st{(G4)(reinterpret_cast<const TT *>(tsrc) + tn),
+                    reinterpret_cast<u32x4_t *>(tabs), nm * WT * (int)sizeof(TT) / 16};
+        StageSeg sc{(G4)(reinterpret_cast<const TT *>(csrc) + tc),
+                    reinterpret_cast<u32x4_t *>(cs), n * WT * (int)sizeof(TT) / 16};
+        stage_segs(r0, r1, st, sc, tid, nthr);
+        for (int q = 0; q < m; ++q) Wl[q * 64] = 0.0;
+    } else if (tabd) {
+        StageSeg none{exg, exd, 0};
+        stage_segs(r0, r1, none, none, tid, nthr);
+        // caller's tables, per-walker layout [W][n][m]
+        for (int idx = tid; idx < nm * WT; idx += nthr) {
+            const int l = idx / nm, e = idx - l * nm, w = w0 + l;
+            tabs[e * WTP + l] = (w < W) ? (TT)MDE_G(double, tabd)[(size_t)w * nm + e] : TT(0);
+        }
+    } else {
+        const void *tsrc = sizeof(TT) == 8 ? (const void *)S.T : (const void *)S.T32;
+        StageSeg st{(G4)(reinterpret_cast<const TT *>(tsrc) + tn),
+                    reinterpret_cast<u32x4_t *>(tabs), nm * WT * (int)sizeof(TT) / 16};
+        StageSeg none{exg, exd, 0};
+        stage_segs(r0, r1, st, none, tid, nthr);
+    }
+    __syncthreads();
+    double acc[NSUM] = {0, 0, 0, 0, 0, 0};
+    {
+        // wave `wave` takes its cost-balanced range of the item, order by order
+        const int ws = __builtin_amdgcn_readfirstlane(wave);
+        const int j0 = bounds[it.wb + 2 * ws], j1 = bounds[it.wb + 2 * ws + 1];
+        for (int k = 1; k <= S.max_order; ++k) {
+            const int a = max(j0, S.order_start[k]), b = min(j1, S.order_start[k + 1]);
+            if (a >= b) continue;
+            if (k <= 2 && ((S.dense_k >> (k - 1)) & 1)) {
+                det_dense_m<TT, MODE>(S, k, it.tile, a, b, tabs, cs, lane, Wl, acc);
+                continue;
+            }
+            const int rb = it.u0;
+            switch (k) {
+                case 1: det_runs64<1, TT, MODE>(S, it.tile, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
+                case 2: det_runs64<2, TT, MODE>(S, it.tile, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
+                case 3: det_direct64<3, TT, MODE>(S, it.tile, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
+                case 4: det_direct64<4, TT, MODE>(S, it.tile, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
+                default: det_generic64<TT, MODE>(S, it.tile, k, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
+            }
+        }
+    }
+    if (MODE != DM_PROPOSE) {
+        __syncthreads();   // LDS is restaged by the next item
+        return;
+    }
+    // e^b[q] of this thread's particles q = wave + i * nw, loaded before the
+    // barrier (their latency overlaps the slowest wave)
+    const auto eg = MDE_G(TT, sizeof(TT) == 8 ? (const void *)I.ev : (const void *)I.ev32) +
+                    (size_t)it.tile * NE * m * WT + lane;
+    double ev[QPT][NE];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const int q = min(wave + i * nw, m - 1);
+#pragma unroll
+        for (int b = 0; b < NE; ++b) ev[i][b] = (double)eg[(size_t)(q * NE + b) * WT];
+    }
+    __syncthreads();
+    // W summed over the waves (wave order) and contracted with e, particle order
+    double part[NE];
+#pragma unroll
+    for (int b = 0; b < NE; ++b) part[b] = 0.0;
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const int q = wave + i * nw;
+        if (q >= m) break;
+        double w = 0.0;
+        for (int v = 0; v < nw; ++v) w += Wall[((size_t)v * m + q) * 64 + lane];
+#pragma unroll
+        for (int b = 0; b < NE; ++b) part[b] = fma(w, ev[i][b], part[b]);
+    }
+    for (int q = wave + QPT * nw; q < m; q += nw) {
+        double w = 0.0;
+        for (int v = 0; v < nw; ++v) w += Wall[((size_t)v * m + q) * 64 + lane];
+#pragma unroll
+        for (int b = 0; b < NE; ++b) part[b] = fma(w, (double)eg[(size_t)(q * NE + b) * WT], part[b]);
+    }
+    __syncthreads();   // W has been read: the LDS holds the reduction now
+    double *red = reinterpret_cast<double *>(tab_raw);   // [nw][64][NSUM]
+    double *red2 = red + (size_t)nw * 64 * NSUM;          // [nw][64][NE]
+#pragma unroll
+    for (int q = 0; q < NSUM; ++q) red[(wave * 64 + lane) * NSUM + q] = acc[q];
+#pragma unroll
+    for (int b = 0; b < NE; ++b) red2[(wave * 64 + lane) * NE + b] = part[b];
+    __syncthreads();
+    const auto pout = MDE_GW(double, S.partial);
+    for (int idx = tid; idx < 64 * NSUM; idx += nthr) {
+        const int l = idx / NSUM, q = idx - l * NSUM;
+        double sum = 0.0;
+        for (int v = 0; v < nw; ++v) sum += red[(v * 64 + l) * NSUM + q];
+        if (q >= 1 && q - 1 < NE)
+            for (int v = 0; v < nw; ++v) sum += red2[(v * 64 + l) * NE + (q - 1)];
+        pout[((size_t)it.slot * 64 + l) * NSUM + q] = sum;
+    }
+    __syncthreads();
+}
+
 template <typename TT, int MODE, int WT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(WT == 64 ? DET64_THREADS : 1024)
 k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
       const int32_t *__restrict__ bounds, ItemQueues qs,
       int ex_cap, const MoveArgs *__restrict__ moves, MoveArgs m1, int32_t *__restrict__ counter,
@@ -490,11 +843,17 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
         it.u1 = __builtin_amdgcn_readfirstlane(it.u1);
         it.slot = __builtin_amdgcn_readfirstlane(it.slot);
         it.wb = __builtin_amdgcn_readfirstlane(it.wb);
+        it.d0 = __builtin_amdgcn_readfirstlane(it.d0);
+        it.d1 = __builtin_amdgcn_readfirstlane(it.d1);
         const InstDev &I = insts[it.inst];
         const SpinDev &S = I.s[it.spin];
         if (MODE == DM_PROPOSE) {
             const int mspin = moves ? moves[it.inst].spin : m1.spin;
             if (mspin != it.spin) continue;
+        }
+        if (WT == 64) {
+            item64<TT, MODE>(it, I, S, exl, tab_raw, bounds, tid, nthr, tab0, tab1);
+            continue;
         }
         const int n = S.n, m = S.m, WTP = S.WTP, W = I.W;
         TT *tabs = reinterpret_cast<TT *>(tab_raw);
@@ -503,11 +862,10 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
         TT *cs = gs + NE * m * WTP;
         const int w0 = it.tile * WT;
         const int nm = n * m;
-        const bool runs = WT == 64;
         // ---- stage the excitation records and the walker tile's tables ----
-        uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
         {
             // records as 4 x 32-bit words (global loads)
+            uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
             const auto exg = MDE_G(uint32_t, S.ex) + (size_t)it.u0 * 4;
             stage_rows<1>(exw, exg, (it.u1 - it.u0) * 4, 1, tid, nthr);
         }
@@ -535,37 +893,19 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
                 }
             } else {
                 const size_t tn = (size_t)it.tile * nm * WT;
-                if (sizeof(TT) == 8)
-                    stage_rows<WT>(tabs, MDE_G(double, S.T) + tn, nm * WT, WTP, tid, nthr);
-                else
-                    stage_rows<WT>(tabs, MDE_G(float, S.T32) + tn, nm * WT, WTP, tid, nthr);
+                const TT *tsrc = reinterpret_cast<const TT *>(sizeof(TT) == 8 ? (const void *)S.T
+                                                                               : (const void *)S.T32);
+                stage_rows<WT>(tabs, MDE_G(TT, tsrc) + tn, nm * WT, WTP, tid, nthr);
             }
         }
         __syncthreads();
         double acc[NSUM] = {0, 0, 0, 0, 0, 0};
-        if (runs) {
-            // wave `slot` takes its cost-balanced range of the item, order by order
-            const int ws = __builtin_amdgcn_readfirstlane(slot);
-            const int j0 = bounds[it.wb + ws], j1 = bounds[it.wb + ws + 1];
-            for (int k = 1; k <= S.max_order; ++k) {
-                const int a = max(j0, S.order_start[k]), b = min(j1, S.order_start[k + 1]);
-                if (a >= b) continue;
-                switch (k) {
-                    case 1: det_runs64<1, TT, MODE>(S, it.tile, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
-                    case 2: det_runs64<2, TT, MODE>(S, it.tile, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
-                    case 3: det_direct64<3, TT, MODE>(S, it.tile, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
-                    case 4: det_direct64<4, TT, MODE>(S, it.tile, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
-                    default: det_generic64<TT, MODE>(S, it.tile, k, a, b, exw, it.u0, tabs, gs, cs, wl, acc); break;
-                }
-            }
-        } else {
-            switch (it.order) {
-                case 1: det_loop<1, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-                case 2: det_loop<2, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-                case 3: det_loop<3, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-                case 4: det_loop<4, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-                default: det_loop<0, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-            }
+        switch (it.order) {
+            case 1: det_loop<1, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+            case 2: det_loop<2, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+            case 3: det_loop<3, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+            case 4: det_loop<4, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+            default: det_loop<0, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
         }
         __syncthreads();   // tables no longer needed: reuse LDS for the reduction
         if (MODE == DM_PROPOSE) {

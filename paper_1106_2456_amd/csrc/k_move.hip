@@ -744,9 +744,9 @@ hipError_t launch_export(hipStream_t st, const InstDev *d_inst, const InstDev &h
     size_t count = h.W;
     if (what == 0) count = (size_t)h.W * S.n * S.n;
     else if (what == 1) count = (size_t)h.W * S.n * S.m;
-    else if (what == 2) count = (size_t)h.W * S.U;
+    else if (what == 2) count = (size_t)h.W * S.n_user;
     hipLaunchKernelGGL(k_export, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, d_inst,
-                       what, spin, dst, perm_user, S.U);
+                       what, spin, dst, perm_user, S.n_user);
     return hipGetLastError();
 }
 

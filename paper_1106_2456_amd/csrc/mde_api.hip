@@ -32,6 +32,8 @@ const char *kVersion = "mde 0.1 (gfx950)";
 
 struct SpinHost {
     int n = 0, m = 0, no = 0, U = 0, max_order = 0;
+    int n_user = 0;     // excitations given by the caller; the dense fill follows
+    int dense_k = 0;    // bit k-1: order k (<= 2) stored dense
     bool have = false;
     std::vector<int> perm;       // internal -> user excitation index
     std::vector<int> iperm;      // user -> internal
@@ -190,17 +192,20 @@ static double order_cost(int k) {
 
 // Relative cost of each excitation in the 64-walker determinant kernel (one
 // wave per excitation), in units of one double excitation inside a run.
-// Orders 1 and 2 are evaluated in runs that share holes and leading
-// particles (a new run pays for its cofactors), orders 3 and 4 one by one.
-// The weights are a least-squares fit of measured per-wave times on MI355X
-// (water-like system, 16 384 wave ranges; rms residual 12 %).
+// Dense orders 1 and 2 cost per excitation of their blocks; sparse orders 1
+// and 2 are evaluated in runs that share holes and leading particles (a new
+// run pays for its cofactors), orders 3 and 4 one by one.  The weights are
+// per-order wave times measured on MI355X with every CU busy (water-like
+// system, 4 096 walkers).
 static void excitation_costs(SpinHost &sp) {
     const int U = (int)sp.ex.size();
     sp.ucost.assign(U, 0.0);
     for (int u = 1; u < U; ++u) {
         const int k = sp.orders[u];
         double w;
-        if (k <= 2) {
+        if (k <= 2 && ((sp.dense_k >> (k - 1)) & 1)) {
+            w = k == 1 ? 0.68 : 0.44;   // dense block: per excitation
+        } else if (k <= 2) {
             const uint32_t pmask = k == 1 ? 0u : 0xffu;
             const bool fresh = sp.orders[u - 1] != k || sp.ex[u].x != sp.ex[u - 1].x ||
                                ((sp.ex[u].z ^ sp.ex[u - 1].z) & pmask) != 0u;
@@ -208,7 +213,7 @@ static void excitation_costs(SpinHost &sp) {
         } else if (k == 3) {
             w = 2.5;
         } else if (k == 4) {
-            w = 7.5;
+            w = 5.1;
         } else {
             w = 6.0 * k * k;
         }
@@ -229,11 +234,22 @@ static int spin_of(const mde_ctx *c, int e, int *row) {
 // then the walker tile's tables (or the reduction scratch, whichever is larger)
 static size_t det_lds(const SpinHost &s, int WT, int threads, int prec, bool propose,
                       int ex_cap = ITEM_MAX) {
-    const int WTP = (WT >= 8) ? WT + 1 : WT;
+    const int WTP = lds_row_stride(WT);
     const size_t esz = prec == 0 ? 8 : 4;
+    const int NE = prec == 0 ? 5 : 4;
     size_t tab = (size_t)s.n * s.m * WTP * esz;
-    if (propose) tab += (size_t)((prec == 0 ? 5 : 4) * s.m + s.n) * WTP * esz;
-    const size_t red = propose ? (size_t)(threads / 64) * WT * NSUM * 8 : 0;
+    size_t red = 0;
+    if (WT == 64) {
+        // c rows, then each wave's FP64 particle weights; the end-of-item
+        // reduction reuses the space
+        if (propose) {
+            tab += (size_t)s.n * WTP * esz + (size_t)(threads / 64) * s.m * 64 * 8;
+            red = (size_t)(threads / 64) * 64 * (NSUM + NE) * 8;
+        }
+    } else if (propose) {
+        tab += (size_t)(NE * s.m + s.n) * WTP * esz;
+        red = (size_t)(threads / 64) * WT * NSUM * 8;
+    }
     return (size_t)ex_cap * 16 + std::max(tab, red);
 }
 
@@ -241,8 +257,38 @@ static size_t det_lds(const SpinHost &s, int WT, int threads, int prec, bool pro
 // item_exc order-2-equivalent excitations (at least one per slot)
 static ItemQueues queue_order(std::vector<WorkItem> &items, const std::vector<double> &cost);
 
-// boundaries of nslot wave ranges of about equal cost over [u0, u1)
-static void wave_bounds(const SpinHost &s, int u0, int u1, int nslot, std::vector<int32_t> &out) {
+// dense block [da, db) of a spin (orders 1 and 2 when stored dense)
+static void dense_range(const SpinHost &s, int &da, int &db) {
+    const bool d1 = s.dense_k & 1, d2 = (s.dense_k >> 1) & 1;
+    da = d1 ? s.order_start[1] : (d2 ? s.order_start[2] : 0);
+    db = d2 ? s.order_start[3] : (d1 ? s.order_start[2] : 0);
+}
+
+// excitations of one wave unit in the dense block of order k (0: sparse):
+// a hole for singles, a fixed share of a hole pair for doubles
+static int dense_unit(const SpinHost &s, int k) {
+    if (k < 1 || k > 2 || !((s.dense_k >> (k - 1)) & 1)) return 0;
+    if (k == 1) return s.m;
+    switch (s.m) {
+        case 8: return Dense2Shape<8>::UNIT;
+        case 12: return Dense2Shape<12>::UNIT;
+        case 16: return Dense2Shape<16>::UNIT;
+        case 20: return Dense2Shape<20>::UNIT;
+        case 24: return Dense2Shape<24>::UNIT;
+        default: return s.m * (s.m - 1) / 2;
+    }
+}
+
+// records an item stages in LDS: those of its sparse range (on 64-walker
+// tiles the dense block needs none and is not part of [u0, u1))
+static int item_records(const SpinHost &s, int u0, int u1, int WT) {
+    (void)s;
+    (void)WT;
+    return u1 - u0;
+}
+
+// boundaries of nslot ranges of about equal cost over [u0, u1)
+static void cost_cuts(const SpinHost &s, int u0, int u1, int nslot, std::vector<int32_t> &out) {
     double tot = 0.0;
     for (int u = u0; u < u1; ++u) tot += s.ucost[u];
     out.push_back(u0);
@@ -254,6 +300,64 @@ static void wave_bounds(const SpinHost &s, int u0, int u1, int nslot, std::vecto
         out.push_back(u);
     }
     out.push_back(u1);
+}
+
+// units of the dense block [da, db): one hole (singles) or one hole pair
+static void dense_units(const SpinHost &s, int d0, int d1, std::vector<int> &starts) {
+    starts.clear();
+    int u = d0;
+    while (u < d1) {
+        starts.push_back(u);
+        const int k = s.orders[u];
+        u += dense_unit(s, k);
+    }
+    starts.push_back(d1);
+}
+
+// Per-wave ranges of a 64-walker item, 2 x nslot entries (first, end):
+// some waves take whole dense units, the others equal-cost pieces of the
+// sparse range, in proportion to the two costs.  Empty ranges are (0, 0).
+static void item_wave_ranges(const SpinHost &s, const WorkItem &it, int nslot,
+                             std::vector<int32_t> &out) {
+    std::vector<int> us;
+    dense_units(s, it.d0, it.d1, us);
+    const int nu = (int)us.size() - 1;
+    double cd = 0.0, cs = 0.0;
+    for (int u = it.d0; u < it.d1; ++u) cd += s.ucost[u];
+    for (int u = it.u0; u < it.u1; ++u) cs += s.ucost[u];
+    int nd = 0;
+    if (nu > 0) {
+        nd = cs > 0.0 ? (int)std::lround(nslot * cd / (cd + cs)) : nslot;
+        nd = std::max(1, std::min({nd, nu, cs > 0.0 ? nslot - 1 : nslot}));
+    }
+    const int ns = nslot - nd;
+    // dense units over nd waves, contiguous, balanced by cost
+    if (nd > 0) {
+        std::vector<double> cum(nu + 1, 0.0);
+        for (int i = 0; i < nu; ++i) {
+            double c = 0.0;
+            for (int u = us[i]; u < us[i + 1]; ++u) c += s.ucost[u];
+            cum[i + 1] = cum[i] + c;
+        }
+        int i0 = 0;
+        for (int w = 0; w < nd; ++w) {
+            int i1 = i0;
+            const double target = cum[nu] * (w + 1) / nd;
+            while (i1 < nu && (w == nd - 1 || cum[i1 + 1] - 0.5 * (cum[i1 + 1] - cum[i1]) <= target)) ++i1;
+            if (w == nd - 1) i1 = nu;
+            out.push_back(us[i0]);
+            out.push_back(us[i1]);
+            i0 = i1;
+        }
+    }
+    if (ns > 0) {
+        std::vector<int32_t> b;
+        cost_cuts(s, it.u0, it.u1, ns, b);
+        for (int w = 0; w < ns; ++w) {
+            out.push_back(b[w]);
+            out.push_back(b[w + 1]);
+        }
+    }
 }
 
 static ItemQueues build_items(const SpinHost &s, int W, int WT, int item_exc, int threads,
@@ -268,48 +372,75 @@ static ItemQueues build_items(const SpinHost &s, int W, int WT, int item_exc, in
     std::vector<double> cost;
     const int U = s.order_start[MAXK + 1];
     if (WT == 64) {
-        // 64-walker tiles: contiguous ranges of the sorted excitation list
-        // (orders mixed) of about equal cost, each split into equal-cost
-        // wave ranges
-        std::vector<double> cum(U + 1, 0.0);
-        for (int u = 1; u < U; ++u) cum[u + 1] = cum[u] + s.ucost[u];
-        const double total = cum[U];
-        int n_it = std::max(1, (int)std::lround(total / std::max(item_exc, 1)));
-        n_it = std::max(n_it, (U - 1 + ITEM_MAX - 1) / ITEM_MAX);
-        std::vector<int> cuts(n_it + 1, 1);
-        cuts[n_it] = U;
-        for (int i = 1; i < n_it; ++i) {
-            const double target = total * i / n_it;
-            int u = (int)(std::lower_bound(cum.begin() + 1, cum.begin() + U + 1, target) - cum.begin());
-            cuts[i] = std::min(std::max(u, cuts[i - 1]), U);
+        // 64-walker tiles: each item takes a contiguous share of the dense
+        // block (whole units) and a contiguous range of the sparse
+        // excitations, sized so the item costs are about equal; the C stream
+        // of the dense block is spread over all items of the tile
+        int da, db;
+        dense_range(s, da, db);
+        const int sp0 = db > da ? db : 1;     // sparse excitations [sp0, U)
+        std::vector<int> us;
+        dense_units(s, da, db, us);
+        const int nu = (int)us.size() - 1;
+        std::vector<double> ucum(nu + 1, 0.0);
+        for (int i = 0; i < nu; ++i) {
+            double c = 0.0;
+            for (int u = us[i]; u < us[i + 1]; ++u) c += s.ucost[u];
+            ucum[i + 1] = ucum[i] + c;
         }
-        // respect the LDS record capacity
-        for (int i = 1; i <= n_it; ++i)
-            if (cuts[i] - cuts[i - 1] > ITEM_MAX) cuts[i] = cuts[i - 1] + ITEM_MAX;
-        if (U > 1 && cuts[n_it] < U) {
-            while (cuts.back() < U) cuts.push_back(std::min(U, cuts.back() + ITEM_MAX));
-            n_it = (int)cuts.size() - 1;
+        std::vector<double> cum(U + 1, 0.0);
+        for (int u = sp0; u < U; ++u) cum[u + 1] = cum[u] + s.ucost[u];
+        const double total = ucum[nu] + cum[U];
+        int n_it = std::max(1, (int)std::lround(total / std::max(item_exc, 1)));
+        n_it = std::max(n_it, (U - sp0 + ITEM_MAX - 1) / ITEM_MAX);
+        n_it = std::min(n_it, std::max(1, nu + (U - sp0)));
+        // dense units: contiguous, by cost
+        std::vector<int> dcut(n_it + 1, 0);
+        for (int i = 1; i < n_it; ++i) {
+            const double target = ucum[nu] * i / n_it;
+            int j = dcut[i - 1];
+            while (j < nu && ucum[j + 1] - 0.5 * (ucum[j + 1] - ucum[j]) <= target) ++j;
+            dcut[i] = j;
+        }
+        dcut[n_it] = nu;
+        // sparse cuts so that item i costs about total / n_it
+        std::vector<int> cuts(n_it + 1, sp0);
+        double dsum = 0.0;
+        for (int i = 1; i < n_it; ++i) {
+            dsum += ucum[dcut[i]] - ucum[dcut[i - 1]];
+            const double target = std::max(0.0, total * i / n_it - dsum) + cum[sp0];
+            int u = (int)(std::lower_bound(cum.begin() + sp0 + 1, cum.begin() + U + 1, target) - cum.begin());
+            cuts[i] = std::min(std::max(u, cuts[i - 1]), U);
+            cuts[i] = std::min(cuts[i], cuts[i - 1] + ITEM_MAX);
+        }
+        cuts[n_it] = U;
+        // the last item's sparse range respects the record capacity
+        while (cuts[n_it] - cuts[n_it - 1] > ITEM_MAX) {
+            cuts.insert(cuts.end() - 1, cuts[n_it - 1] + ITEM_MAX);
+            dcut.insert(dcut.end() - 1, nu);
+            ++n_it;
         }
         for (int t = 0; t < n_tiles; ++t) {
             tile_slot[t] = (int)per.size();
             for (int i = 0; i < n_it; ++i) {
-                const int u0 = cuts[i], u1 = cuts[i + 1];
-                if (u1 <= u0) continue;
                 WorkItem it{};
                 it.inst = 0;
                 it.spin = spin;
                 it.tile = t;
                 it.order = 0;
-                it.u0 = u0;
-                it.u1 = u1;
+                it.u0 = cuts[i];
+                it.u1 = cuts[i + 1];
+                it.d0 = us[dcut[i]];
+                it.d1 = us[dcut[i + 1]];
+                if (it.u1 <= it.u0 && it.d1 <= it.d0) continue;
                 it.slot = (int)per.size();
                 it.wb = -1;
                 if (bounds) {
                     it.wb = (int)bounds->size();
-                    wave_bounds(s, u0, u1, nslot, *bounds);
+                    item_wave_ranges(s, it, nslot, *bounds);
                 }
                 per.push_back(it);
-                cost.push_back(cum[u1] - cum[u0]);
+                cost.push_back(cum[it.u1] - cum[it.u0] + ucum[dcut[i + 1]] - ucum[dcut[i]]);
             }
         }
     } else {
@@ -393,22 +524,29 @@ static int item_size_for(const mde_ctx *c, const SpinHost &sp, int W, int WT, in
     return std::max(sz, 4 * nslot);
 }
 
+// threads of a determinant block for walker tile WT, and the most it may have
+static int max_threads(int WT) { return WT == 64 ? DET64_THREADS : 1024; }
+static int default_threads(int WT) { return WT == 64 ? DET64_THREADS : (WT >= 16 ? 1024 : 256); }
+
 static Plan default_plan(const mde_ctx *c, int W) {
     Plan p{};
     const size_t esz = c->d.precision == 0 ? 8 : 4;
-    // largest walker tile whose tables fit in ~112 KB of LDS for both spins
+    // largest walker tile whose tables fit in LDS for both spins: the
+    // 64-walker block (tables, c and the waves' particle weights) in the
+    // 160 KB of a CU, smaller tiles in ~112 KB
     int WT = 64;
     for (int s = 0; s < 2; ++s) {
         const SpinHost &sp = c->sp[s];
         const size_t per_w = (size_t)(sp.n * sp.m + (esz == 8 ? 5 : 4) * sp.m + sp.n) * esz;
         int wt = 64;
-        while (wt > 1 && per_w * (wt + (wt >= 8 ? 1 : 0)) > 112 * 1024) wt /= 2;
+        if (det_lds(sp, 64, DET64_THREADS, c->d.precision, true) > 160 * 1024) wt = 32;
+        while (wt > 1 && wt < 64 && per_w * (wt + (wt >= 8 ? 1 : 0)) > 112 * 1024) wt /= 2;
         WT = std::min(WT, wt);
     }
     WT = std::min(WT, std::max(1, pow2_floor(std::max(W, 1))));
     p.WT = WT;
     for (int s = 0; s < 2; ++s) {
-        p.threads[s] = (WT >= 16) ? 1024 : 256;
+        p.threads[s] = default_threads(WT);
         const size_t lds = det_lds(c->sp[s], WT, p.threads[s], c->d.precision, true);
         p.item_exc[s] = item_size_for(c, c->sp[s], W, WT, p.threads[s], lds);
     }
@@ -419,7 +557,7 @@ static void apply_default_plan(mde_ctx *c, int W) {
     const Plan p = default_plan(c, W);
     if (!c->user_wt) c->WT = p.WT;
     for (int s = 0; s < 2; ++s) {
-        if (!c->user_thr[s]) c->sp[s].threads = (c->WT >= 16) ? 1024 : 256;
+        if (!c->user_thr[s]) c->sp[s].threads = default_threads(c->WT);
         if (!c->user_item[s]) {
             const size_t lds = det_lds(c->sp[s], c->WT, c->sp[s].threads, c->d.precision, true);
             c->sp[s].item_exc = item_size_for(c, c->sp[s], W, c->WT, c->sp[s].threads, lds);
@@ -438,7 +576,7 @@ static std::vector<Plan> candidate_plans(const mde_ctx *c, int W) {
     for (int a = 0; a < 3; ++a) {
         if (a > 0 && wts[a] == wts[a - 1]) continue;
         for (int b = 0; b < 3; ++b) {
-            if (thr[b] < wts[a]) continue;
+            if (thr[b] < wts[a] || thr[b] > max_threads(wts[a])) continue;
             for (int e = 0; e < 3; ++e) {
                 Plan p{};
                 p.WT = wts[a];
@@ -592,11 +730,12 @@ static mde_status apply_plan(mde_ctx *c) {
         sp.queues = q;
         sp.tile_slot = ts;
         S.WT = c->WT;
-        S.WTP = (c->WT >= 8) ? c->WT + 1 : c->WT;
+        S.WTP = lds_row_stride(c->WT);
         S.n_tiles = (c->W + c->WT - 1) / c->WT;
         S.n_slots = (int)items.size();
         sp.ex_cap = 16;
-        for (const WorkItem &it : items) sp.ex_cap = std::max(sp.ex_cap, it.u1 - it.u0);
+        for (const WorkItem &it : items)
+            sp.ex_cap = std::max(sp.ex_cap, item_records(sp, it.u0, it.u1, c->WT));
         sp.lds_prop = det_lds(sp, c->WT, sp.threads, c->d.precision, true, sp.ex_cap);
         sp.lds_val = det_lds(sp, c->WT, sp.threads, c->d.precision, false, sp.ex_cap);
         if (sp.lds_prop > 160 * 1024)
@@ -789,6 +928,48 @@ mde_status mde_set_excitations(mde_ctx *c, int32_t spin, int32_t n_exc, const in
         }
         max_order = std::max(max_order, k);
     }
+    // Dense storage of orders 1 and 2: when most of the possible singles
+    // (doubles) of a small virtual space are present, the missing ones are
+    // appended with no determinant referring to them (their CI weight is
+    // zero), so that the 64-walker kernel evaluates each hole set's block as
+    // a whole, without records.
+    sp.n_user = n_exc;
+    sp.dense_k = 0;
+    if (dense_m_supported(sp.m)) {
+        const int m = sp.m;
+        const int NP = m * (m - 1) / 2;
+        std::vector<char> have1((size_t)n * m, 0), have2((size_t)(n * (n - 1) / 2) * NP, 0);
+        auto pair_idx = [](int a, int b, int N) { return a * (2 * N - a - 1) / 2 + (b - a - 1); };
+        int c1 = 0, c2 = 0;
+        for (int u = 1; u < n_exc; ++u) {
+            const Key &K = keys[u];
+            if (K.k == 1) {
+                have1[(size_t)K.h[0] * m + K.p[0]] = 1;
+                ++c1;
+            } else if (K.k == 2) {
+                have2[(size_t)pair_idx(K.h[0], K.h[1], n) * NP + pair_idx(K.p[0], K.p[1], m)] = 1;
+                ++c2;
+            }
+        }
+        const bool d2 = c2 > 0 && n >= 2 && c2 >= 0.6 * (n * (n - 1) / 2) * NP;
+        // with dense doubles the singles are filled too (at most n m of
+        // them), so the sparse excitations form one range after the block
+        const bool d1 = c1 > 0 && (c1 >= 0.6 * n * m || d2);
+        if (d1)
+            for (int h = 0; h < n; ++h)
+                for (int p = 0; p < m; ++p)
+                    if (!have1[(size_t)h * m + p])
+                        keys.push_back(Key{1, {h}, {p}, (int)keys.size()});
+        if (d2)
+            for (int h0 = 0; h0 < n; ++h0)
+                for (int h1 = h0 + 1; h1 < n; ++h1)
+                    for (int p0 = 0; p0 < m; ++p0)
+                        for (int p1 = p0 + 1; p1 < m; ++p1)
+                            if (!have2[(size_t)pair_idx(h0, h1, n) * NP + pair_idx(p0, p1, m)])
+                                keys.push_back(Key{2, {h0, h1}, {p0, p1}, (int)keys.size()});
+        sp.dense_k = (d1 ? 1 : 0) | (d2 ? 2 : 0);
+        n_exc = (int)keys.size();
+    }
     std::vector<int> order((size_t)n_exc);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin() + 1, order.end(), [&](int x, int y) {
@@ -828,6 +1009,7 @@ mde_status mde_set_excitations(mde_ctx *c, int32_t spin, int32_t n_exc, const in
     std::vector<int> cnt(nm + 1, 0);
     for (int i = 0; i < n_exc; ++i) {
         const Key &K = keys[order[i]];
+        if (K.user >= sp.n_user) continue;   // dense fill: no determinant refers to it
         for (int j = 0; j < K.k; ++j)
             for (int l = 0; l < K.k; ++l) cnt[K.h[j] * sp.m + K.p[l] + 1]++;
     }
@@ -837,6 +1019,7 @@ mde_status mde_set_excitations(mde_ctx *c, int32_t spin, int32_t n_exc, const in
     std::vector<int> pos(cnt.begin(), cnt.end() - 1);
     for (int i = 0; i < n_exc; ++i) {
         const Key &K = keys[order[i]];
+        if (K.user >= sp.n_user) continue;
         for (int j = 0; j < K.k; ++j)
             for (int l = 0; l < K.k; ++l)
                 sp.inv_ent[pos[K.h[j] * sp.m + K.p[l]]++] = (i << 10) | (K.k << 6) | (j << 3) | l;
@@ -856,7 +1039,7 @@ mde_status mde_set_ci(mde_ctx *c, int64_t n_det, const double *coef, const int32
     const int *idx[2] = {up_idx, dn_idx};
     for (int64_t I = 0; I < n_det; ++I)
         for (int s = 0; s < 2; ++s)
-            if (idx[s][I] < 0 || idx[s][I] >= c->sp[s].U)
+            if (idx[s][I] < 0 || idx[s][I] >= c->sp[s].n_user)
                 MDE_FAIL(c, MDE_INVALID, "determinant %lld: excitation index out of range", (long long)I);
     c->n_det = n_det;
     c->coef.assign(coef, coef + n_det);
@@ -967,6 +1150,8 @@ mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
         S.no = sp.no;
         S.U = sp.U;
         S.max_order = sp.max_order;
+        S.dense_k = sp.dense_k;
+        S.n_user = sp.n_user;
         for (int k = 0; k < MAXK + 2; ++k) S.order_start[k] = sp.order_start[k];
         MDE_HIP(c, hipMemcpy((void *)S.ex, sp.ex.data(), sizeof(uint4) * sp.U, hipMemcpyHostToDevice));
         MDE_HIP(c, hipMemcpy((void *)S.ci_seg, sp.ci_seg.data(), sizeof(int) * (sp.U + 1),
@@ -1160,14 +1345,26 @@ mde_status mde_set_plan(mde_ctx *c, int32_t spin, int32_t walker_tile, int32_t i
     if (walker_tile) {
         if (walker_tile < 1 || walker_tile > 64 || (walker_tile & (walker_tile - 1)))
             MDE_FAIL(c, MDE_INVALID, "walker tile must be a power of two in 1..64");
+    }
+    const int wt_new = walker_tile ? walker_tile : c->WT;
+    if (threads) {
+        if (threads < 64 || threads > max_threads(wt_new) || threads % 64)
+            MDE_FAIL(c, MDE_INVALID, "bad thread count (64..%d, a multiple of 64, for walker tile %d)",
+                     max_threads(wt_new), wt_new);
+    }
+    if (c->user_thr[1 - spin] && c->sp[1 - spin].threads > max_threads(wt_new))
+        MDE_FAIL(c, MDE_INVALID, "the other spin's thread count exceeds %d for walker tile %d",
+                 max_threads(wt_new), wt_new);
+    if (walker_tile) {
         c->WT = walker_tile;
         c->user_wt = true;
     }
     if (threads) {
-        if (threads < 64 || threads > 1024 || threads % 64) MDE_FAIL(c, MDE_INVALID, "bad thread count");
         c->sp[spin].threads = threads;
         c->user_thr[spin] = true;
     }
+    for (int s = 0; s < 2; ++s)
+        if (c->sp[s].threads > max_threads(c->WT)) c->sp[s].threads = default_threads(c->WT);
     if (item_exc) {
         if (item_exc < 1) MDE_FAIL(c, MDE_INVALID, "bad item size");
         c->sp[spin].item_exc = item_exc;
@@ -1180,6 +1377,40 @@ mde_status mde_set_plan(mde_ctx *c, int32_t spin, int32_t walker_tile, int32_t i
     if (st) return st;
     c->initialized = false;   // R and C layouts depend on the tile: re-init needed
     MDE_HIP(c, launch_init_misc(c->stream, c->d_inst, c->h));
+    return MDE_OK;
+}
+
+mde_status mde_debug_items(const mde_ctx *c, int32_t spin, int32_t W, int32_t walker_tile,
+                           int32_t item_exc, int32_t threads, int32_t *items, int32_t items_cap,
+                           int32_t *n_items, int32_t *ranges, int32_t ranges_cap,
+                           int32_t *n_ranges, int32_t *layout) {
+    if (!c || spin < 0 || spin > 1 || W < 1 || item_exc < 1 || !n_items || !n_ranges)
+        return MDE_INVALID;
+    if (walker_tile < 1 || walker_tile > 64 || (walker_tile & (walker_tile - 1))) return MDE_INVALID;
+    if (threads < walker_tile || threads > max_threads(walker_tile) || threads % 64) return MDE_INVALID;
+    const SpinHost &sp = c->sp[spin];
+    if (!sp.have || sp.ucost.empty()) return MDE_STATE;
+    std::vector<WorkItem> it;
+    std::vector<int> ts;
+    std::vector<int32_t> bd;
+    build_items(sp, W, walker_tile, item_exc, threads, it, ts, spin, &bd);
+    *n_items = (int32_t)it.size();
+    *n_ranges = (int32_t)bd.size();
+    if (layout) {
+        int da, db;
+        dense_range(sp, da, db);
+        layout[0] = sp.U;
+        layout[1] = da;
+        layout[2] = db;
+        layout[3] = sp.dense_k;
+    }
+    if ((int)it.size() > items_cap || (int)bd.size() > ranges_cap) return MDE_NOMEM;
+    for (size_t i = 0; i < it.size(); ++i) {
+        const WorkItem &w = it[i];
+        const int32_t v[10] = {w.inst, w.spin, w.tile, w.order, w.u0, w.u1, w.slot, w.wb, w.d0, w.d1};
+        if (items) std::copy(v, v + 10, items + 10 * i);
+    }
+    if (ranges) std::copy(bd.begin(), bd.end(), ranges);
     return MDE_OK;
 }
 
@@ -1416,7 +1647,7 @@ mde_status mde_group_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *by
     cv.take<InstDev>(n);
     cv.take<MoveArgs>(n);
     cv.take<WorkItem>(max_items);
-    cv.take<int32_t>(max_items * (1024 / 64 + 1));
+    cv.take<int32_t>(max_items * 2 * (1024 / 64));
     *bytes = cv.off + 256;
     return MDE_OK;
 }
@@ -1442,9 +1673,10 @@ static mde_status group_rebuild(mde_group *g) {
                 if (g->WT == 64) {
                     double cst = 0.0;
                     for (int u = it.u0; u < it.u1; ++u) cst += c->sp[s].ucost[u];
+                    for (int u = it.d0; u < it.d1; ++u) cst += c->sp[s].ucost[u];
                     cost.push_back(cst);
                     it.wb = (int)bounds.size();
-                    wave_bounds(c->sp[s], it.u0, it.u1, g->threads / 64, bounds);
+                    item_wave_ranges(c->sp[s], it, g->threads / 64, bounds);
                 } else {
                     cost.push_back(order_cost(it.order) * (it.u1 - it.u0) * c->WT);
                 }
@@ -1507,7 +1739,7 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
         for (int s = 0; s < 2; ++s) thr = std::max(thr, ctxs[i]->sp[s].threads);
     }
     g->WT = ctxs[0]->WT;
-    g->threads = std::max(thr, g->WT);
+    g->threads = std::min(std::max(thr, g->WT), max_threads(g->WT));
     Carver cv{(char *)dev};
     g->d_insts = cv.take<InstDev>(n);
     g->d_moves = cv.take<MoveArgs>(n);
@@ -1518,7 +1750,7 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
         max_items += mi;
     }
     g->d_items = cv.take<WorkItem>(max_items);
-    g->d_bounds = cv.take<int32_t>(max_items * (1024 / 64 + 1));
+    g->d_bounds = cv.take<int32_t>(max_items * 2 * (1024 / 64));
     if (hipHostMalloc((void **)&g->pinned, sizeof(MoveArgs) * n * mde_group::RING) != hipSuccess) {
         delete g;
         return MDE_NOMEM;

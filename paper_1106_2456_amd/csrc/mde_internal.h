@@ -16,9 +16,13 @@ constexpr int NSUM = 6;      // sums over excitations: N, q-term, x, y, z, lapla
 // `slot` of that instance and spin.  64-walker tiles: the range may span
 // several orders and wave w of the block takes [bounds[wb + w],
 // bounds[wb + w + 1]); smaller tiles: one order `order`, slot-strided.
+// A work item: walker tile `tile` of instance `inst`, excitations [u0, u1)
+// (records staged in LDS) and, on 64-walker tiles, also the dense-block
+// excitations [d0, d1); wb indexes the per-wave (first, end) ranges.
 struct WorkItem {
     int32_t inst, spin, tile, order;
     int32_t u0, u1, slot, wb;
+    int32_t d0, d1;
 };
 
 // Per-spin device view of one instance.  Internal excitation order: sorted
@@ -28,7 +32,10 @@ struct SpinDev {
     int32_t WT, WTP, n_tiles, n_slots;   // walker tile, LDS row stride
     int32_t order_start[MAXK + 2];       // first u of each order (k = 0..9)
     int32_t max_order;
-    int32_t pad0;
+    // Orders stored dense (bit k-1 for order k <= 2): every excitation of
+    // the order is present, hole sets ascending, particles ascending within
+    // a hole set, so a hole set's block is evaluated without records.
+    int32_t dense_k;
     const uint4 *ex;          // [U] packed: bytes 0..7 holes, 8..15 particles - n
     const int32_t *ci_seg;    // [U+1] CI terms of this spin's excitation u
     const int32_t *ci_other;  // [n_det] other spin's excitation, per term
@@ -54,8 +61,39 @@ struct SpinDev {
     const int4 *pieces;      // [n_pieces] (u, k0, k1, -) pieces of long CI segments
     const int4 *longs;       // [n_longs] (u, first piece, end piece, -)
     double *pc_part;         // [n_pieces][n_tiles][WT] partial sums of the pieces
-    int32_t n_chunks, n_pieces, n_longs, pad1;
+    int32_t n_chunks, n_pieces, n_longs;
+    int32_t n_user;          // excitations given by the caller (the dense fill follows them)
 };
+
+// virtual-space sizes m for which the 64-walker kernel has a dense block
+// evaluator of orders 1 and 2 (its particle loops are unrolled over m)
+__host__ __device__ constexpr bool dense_m_supported(int m) {
+    return m == 8 || m == 12 || m == 16 || m == 20 || m == 24;
+}
+
+// Units of a dense block handed to one wave: a single's unit is one hole
+// (M excitations), a double's one hole pair (NP = M (M - 1) / 2).  The
+// ring of CI weights in flight has PD entries, PD dividing NP, so an
+// excitation's ring slot depends on its place in the pair only.  (The pair
+// body is straight-line code: one unit per pair keeps the ring in fixed
+// registers across pairs, with no wait for all loads at the loop edge.)
+template <int M>
+struct Dense2Shape {
+    static constexpr int NP = M * (M - 1) / 2;
+    static constexpr int G = 1;
+    static constexpr int UNIT = NP / G;
+    static constexpr int PD = M == 8 ? 28 : M == 12 ? 33 : M == 16 ? 40 : M == 20 ? 38 : 46;
+    static_assert(NP % G == 0 && UNIT % PD == 0, "dense unit shape");
+};
+
+// first excitation and end of the dense block of a spin (orders 1 and 2
+// when stored dense; singles are filled whenever doubles are, so the block
+// is one range); da == db when there is none
+__host__ __device__ inline void dense_range(const SpinDev &S, int &da, int &db) {
+    const bool d1 = S.dense_k & 1, d2 = (S.dense_k >> 1) & 1;
+    da = d1 ? S.order_start[1] : (d2 ? S.order_start[2] : 0);
+    db = d2 ? S.order_start[3] : (d1 ? S.order_start[2] : 0);
+}
 
 struct InstDev {
     SpinDev s[2];
@@ -99,6 +137,15 @@ enum DetMode { DM_PROPOSE = 0, DM_VALUES = 1 };
 
 // Largest excitation range of one work item (its records are staged in LDS).
 constexpr int ITEM_MAX = 1024;
+// threads of a 64-walker determinant block: eight waves, so each wave may
+// hold a hole set's table rows in registers (up to 256 VGPRs)
+constexpr int DET64_THREADS = 512;
+// LDS row stride of a walker tile's tables: 64-walker rows are read whole
+// (one 512-byte row per wave) and need no padding; smaller tiles pad by one
+// element against bank conflicts between lanes reading different rows
+__host__ __device__ constexpr int lds_row_stride(int WT) {
+    return WT == 64 ? 64 : (WT >= 8 ? WT + 1 : WT);
+}
 
 // The chip's workgroups are dispatched round-robin over its 8 accelerator
 // dies (XCDs), each with its own L2.  Work on walker tile t is placed on XCD
