@@ -632,6 +632,90 @@ __device__ __forceinline__ void stage_segs(const StageSeg &s0, const StageSeg &s
     }
 }
 
+// End of a 64-walker item whose proposal is formed in the determinant
+// kernel (FP64 current-table frame).  With W_p the per-particle weights
+// summed over the waves and V_r = sum_p W_p Tab[r][p], the e-terms are
+//   sum_p W_p q_p     = sum_r a'_r V_r - sum_p W_p phi'_p
+//   sum_p W_p w^a_p   = sum_p W_p d^a_V[p] - sum_r d^a_O[r] V_r
+// (q = a'^T T_V - phi'_V, w^a = d^a_V - d^a_O^T T_V), so only the new
+// orbital values of the walker are read.  The quantities the commit needs
+// (c, rho, r = a'^T A^-1 - e_i^T, q) are formed by the finishing kernel.
+__device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstDev &I,
+                                                 const SpinDev &S, const MoveArgs &mv,
+                                                 const double *tabs, const double *cs,
+                                                 double *Wall, double *Vs,
+                                                 unsigned char *tab_raw, const double (&acc)[NSUM],
+                                                 int tid, int nthr) {
+    constexpr int WT = 64, WTP = lds_row_stride(64);
+    const int n = S.n, m = S.m, no = S.no, W = I.W, nm = n * m;
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    const int w0 = it.tile * WT;
+    const auto orb = MDE_G(double, mv.new_orb);
+    __syncthreads();   // all waves done: W final, Tab and c intact
+    for (int idx = tid; idx < m * 64; idx += nthr) {
+        const int q = idx >> 6, l = idx & 63;
+        double w = 0.0;
+        for (int v = 0; v < nw; ++v) w += Wall[((size_t)v * m + q) * 64 + l];
+        Wall[idx] = w;     // this thread alone reads and writes entry (q, l)
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * 64; idx += nthr) {
+        const int r = idx >> 6, l = idx & 63;
+        double v = 0.0;
+        for (int q = 0; q < m; ++q) v = fma(Wall[q * 64 + l], tabs[(r * m + q) * WTP + l], v);
+        Vs[idx] = v;
+    }
+    __syncthreads();
+    // component b = 0..4 of walker lane l: thread (b, l), b = wave, wave + nw;
+    // the walker's 2 x no values are read in groups of 8 loads
+    double ctr[2] = {0.0, 0.0};
+    const int w = w0 + lane;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int b = wave + i * nw;
+        if (b < 5 && w < W) {
+            const auto ob = orb + ((size_t)w * 5 + b) * no;
+            double so = 0.0, sv = 0.0;
+            int k = 0;
+            for (; k + 8 <= no; k += 8) {
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = ob[k + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int kk = k + u;
+                    if (kk < n) so = fma(x[u], Vs[kk * 64 + lane], so);
+                    else sv = fma(Wall[(kk - n) * 64 + lane], x[u], sv);
+                }
+            }
+            for (; k < no; ++k) {
+                const double x = ob[k];
+                if (k < n) so = fma(x, Vs[k * 64 + lane], so);
+                else sv = fma(Wall[(k - n) * 64 + lane], x, sv);
+            }
+            ctr[i] = b == 0 ? so - sv : sv - so;
+        }
+    }
+    __syncthreads();   // Tab, W, V read: the LDS holds the reduction now
+    double *red = reinterpret_cast<double *>(tab_raw);   // [nw][NSUM][64], then [5][64]
+    double *red2 = red + (size_t)nw * NSUM * 64;
+#pragma unroll
+    for (int q = 0; q < NSUM; ++q) red[((size_t)wave * NSUM + q) * 64 + lane] = acc[q];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        if (wave + i * nw < 5) red2[(wave + i * nw) * 64 + lane] = ctr[i];
+    __syncthreads();
+    const auto pout = MDE_GW(double, S.partial);
+    for (int idx = tid; idx < 64 * NSUM; idx += nthr) {
+        const int l = idx / NSUM, q = idx - l * NSUM;
+        double sum = 0.0;
+        for (int v = 0; v < nw; ++v) sum += red[((size_t)v * NSUM + q) * 64 + l];
+        if (q >= 1) sum += red2[(q - 1) * 64 + l];
+        pout[((size_t)it.slot * 64 + l) * NSUM + q] = sum;
+    }
+    __syncthreads();
+}
+
 // One work item on a 64-walker tile.  LDS: [records][Tab n*m rows][c n rows]
 // [W: per wave, m rows of 64 FP64 particle weights].  Each wave evaluates
 // its range (dense units or a piece of the sparse range) order by order;
@@ -641,7 +725,7 @@ __device__ __forceinline__ void stage_segs(const StageSeg &s0, const StageSeg &s
 // walker in a fixed order.
 template <typename TT, int MODE>
 __device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, const SpinDev &S,
-                                       uint4 *exl, unsigned char *tab_raw,
+                                       const MoveArgs &mv, uint4 *exl, unsigned char *tab_raw,
                                        const int32_t *__restrict__ bounds, int tid, int nthr,
                                        const double *tab0, const double *tab1) {
     constexpr int WT = 64, WTP = lds_row_stride(64);
@@ -649,10 +733,15 @@ __device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, con
     constexpr int QPT = 3;        // e-values prefetched per thread (particles wave, wave+nw, ..)
     const int n = S.n, m = S.m, W = I.W, nm = n * m;
     const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    // FP64 proposals formed here: c from A^-1, the e-terms from the new
+    // orbital values (no e^b rows), and the tile's first item writes the
+    // move's quantities for the commit and the finish
+    const bool fused = MODE == DM_PROPOSE && sizeof(TT) == 8 && (mv.mode & MV_FUSED);
     TT *tabs = reinterpret_cast<TT *>(tab_raw);
     TT *cs = tabs + nm * WTP;
     double *Wall = reinterpret_cast<double *>(cs + n * WTP);
     double *Wl = Wall + (size_t)wave * m * 64 + lane;
+    double *Vs = Wall + (size_t)nw * m * 64;    // [n][64] (fused proposals)
     uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
     // records of the item's sparse range [u0, u1) (the dense block needs
     // none): record u at exw[4 * (u - u0)]
@@ -664,7 +753,20 @@ __device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, con
     const int w0 = it.tile * WT;
     const size_t tn = (size_t)it.tile * nm * WT, tc = (size_t)it.tile * n * WT;
     const double *tabd = it.spin == 0 ? tab0 : tab1;
-    if (MODE == DM_PROPOSE) {
+    if (fused) {
+        // c = A^-1 e_i: column `row` of each walker's inverse (its rows are
+        // contiguous per walker)
+        const StageSeg none{exg, exd, 0};
+        StageSeg st{(G4)(MDE_G(double, S.T) + tn), reinterpret_cast<u32x4_t *>(tabs),
+                    nm * WT * 8 / 16};
+        const int nn = n * n, row = mv.row;
+        for (int idx = tid; idx < n * WT; idx += nthr) {
+            const int r = idx >> 6, l = idx & 63, w = w0 + l;
+            cs[idx] = (TT)(w < W ? MDE_G(double, S.B)[(size_t)w * nn + r * n + row] : 0.0);
+        }
+        stage_segs(r0, r1, st, none, tid, nthr);
+        for (int q = 0; q < m; ++q) Wl[q * 64] = 0.0;
+    } else if (MODE == DM_PROPOSE) {
         const void *tsrc = sizeof(TT) == 8 ? (const void *)S.T : (const void *)I.Tp32;
         const void *csrc = sizeof(TT) == 8 ? (const void *)I.cc : (const void *)I.cc32;
         StageSeg st{(G4)(reinterpret_cast<const TT *>(tsrc) + tn),
@@ -714,6 +816,12 @@ __device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, con
     if (MODE != DM_PROPOSE) {
         __syncthreads();   // LDS is restaged by the next item
         return;
+    }
+    if constexpr (sizeof(TT) == 8) {
+        if (fused) {
+            item64_fused_end(it, I, S, mv, tabs, cs, Wall, Vs, tab_raw, acc, tid, nthr);
+            return;
+        }
     }
     // e^b[q] of this thread's particles q = wave + i * nw, loaded before the
     // barrier (their latency overlaps the slowest wave)
@@ -852,7 +960,8 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
             if (mspin != it.spin) continue;
         }
         if (WT == 64) {
-            item64<TT, MODE>(it, I, S, exl, tab_raw, bounds, tid, nthr, tab0, tab1);
+            const MoveArgs mv = moves ? moves[it.inst] : m1;
+            item64<TT, MODE>(it, I, S, mv, exl, tab_raw, bounds, tid, nthr, tab0, tab1);
             continue;
         }
         const int n = S.n, m = S.m, WTP = S.WTP, W = I.W;
@@ -1263,36 +1372,9 @@ hipError_t launch_nsum(hipStream_t st, const InstDev *d_inst, const InstDev &h,
 //   ratio = rho N' / N_old,   grad^a = ((kappa^a / rho) N' + G^a) / N'.
 // ---------------------------------------------------------------------------
 
-__global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves,
-                         MoveArgs m1) {
-    const int inst = blockIdx.y;
-    const InstDev &I = insts[inst];
-    const MoveArgs mv = moves ? moves[inst] : m1;
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= I.W) return;
-    const SpinDev &S = I.s[mv.spin];
-    const int WT = S.WT, t = w / WT, wl = w - t * WT;
-    const double C0 = MDE_G(double, S.C)[(size_t)t * S.U * WT + wl];
-    double sum[NSUM] = {C0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
-    const auto part = MDE_G(double, S.partial);
-    // slots in order; the loads of four slots are issued before they are added
-    int s = s0;
-    for (; s + 4 <= s1; s += 4) {
-        double v[4][NSUM];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int q = 0; q < NSUM; ++q) v[k][q] = part[((size_t)(s + k) * WT + wl) * NSUM + q];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int q = 0; q < NSUM; ++q) sum[q] += v[k][q];
-    }
-    for (; s < s1; ++s) {
-#pragma unroll
-        for (int q = 0; q < NSUM; ++q) sum[q] += part[((size_t)s * WT + wl) * NSUM + q];
-    }
+// the walker's results from its summed partials (C_0 included in sum[0])
+__device__ __forceinline__ void finish_walker(const InstDev &I, const MoveArgs &mv, int w,
+                                              const double (&sum)[NSUM]) {
     const double rho = I.rho[w];
     const auto kap = MDE_G(double, I.kap) + (size_t)w * 4;
     double ratio, rNp, d[4];
@@ -1327,12 +1409,154 @@ __global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__re
     if (mv.status && bits) mv.status[w] |= bits;
 }
 
+__global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves,
+                         MoveArgs m1) {
+    const int inst = blockIdx.y;
+    const InstDev &I = insts[inst];
+    const MoveArgs mv = moves ? moves[inst] : m1;
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= I.W) return;
+    const SpinDev &S = I.s[mv.spin];
+    const int WT = S.WT, t = w / WT, wl = w - t * WT;
+    const double C0 = MDE_G(double, S.C)[(size_t)t * S.U * WT + wl];
+    double sum[NSUM] = {C0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
+    const auto part = MDE_G(double, S.partial);
+    // slots in order; the loads of four slots are issued before they are added
+    int s = s0;
+    for (; s + 4 <= s1; s += 4) {
+        double v[4][NSUM];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) v[k][q] = part[((size_t)(s + k) * WT + wl) * NSUM + q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) sum[q] += v[k][q];
+    }
+    for (; s < s1; ++s) {
+#pragma unroll
+        for (int q = 0; q < NSUM; ++q) sum[q] += part[((size_t)s * WT + wl) * NSUM + q];
+    }
+    finish_walker(I, mv, w, sum);
+}
+
 hipError_t launch_finish(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int32_t *counter) {
     (void)counter;
     const int threads = 64;
     hipLaunchKernelGGL(k_finish, dim3((maxW + threads - 1) / threads, n_inst), dim3(threads), 0, st,
                        d_insts, d_moves, m1);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Finish of a proposal formed in the determinant kernel (FP64, 64-walker
+// tiles), four threads per walker: c = A^-1 e_i, rho = a'.c and
+// kappa^a = d^a_O.c (matrix determinant lemma, Sec. III), the results from
+// the tile's partials (as k_finish), and for the commit c,
+// r = a'^T A^-1 - e_i^T and the new orbital row (the commit forms
+// q = a'^T T_V - phi'_V itself).
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_post(const InstDev *__restrict__ insts, MoveArgs mv) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[mv.spin];
+    constexpr int WT = 64, NMAX = 8, NG = 4;
+    const int t = blockIdx.x;              // block t runs on die t % 8, as the tile's items
+    if (t >= S.n_tiles) return;
+    const int n = S.n, no = S.no, nn = n * n, row = mv.row, W = I.W;
+    // four threads per walker: thread g takes rows k = g, g + 4 of A^-1,
+    // component(s) b = g (, 4) of the orbital block, a quarter of the row
+    // copy, and g = 1 the partial sums
+    const int l = threadIdx.x & 63, g = threadIdx.x >> 6, w = t * WT + l;
+    const bool live = w < W;
+    __shared__ double c_s[NMAX][WT], rr_s[NG][NMAX][WT], o_s[5][NMAX][WT], sum_s[NSUM][WT];
+    const auto orb = MDE_G(double, mv.new_orb) + (size_t)(live ? w : 0) * 5 * no;
+    const auto B = MDE_G(double, S.B) + (size_t)(live ? w : 0) * nn;
+    double rr[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) rr[j] = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = g + h * NG;
+        if (k < n && live) {
+            double bk[NMAX];
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j) bk[j] = j < n ? B[k * n + j] : 0.0;
+            const double ak = orb[k];
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j) rr[j] = fma(ak, bk[j], rr[j]);
+            double ck = 0.0;
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j)
+                if (j == row) ck = bk[j];
+            c_s[k][l] = ck;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) rr_s[g][j][l] = rr[j];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int b = g + h * NG;
+        if (b < 5 && live) {
+            double ob[NMAX];
+#pragma unroll
+            for (int r = 0; r < NMAX; ++r) ob[r] = r < n ? orb[b * no + r] : 0.0;
+#pragma unroll
+            for (int r = 0; r < NMAX; ++r) o_s[b][r][l] = ob[r];
+        }
+    }
+    if (g == 1 && live) {
+        const double C0 = MDE_G(double, S.C)[(size_t)t * S.U * WT + l];
+        double sum[NSUM] = {C0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
+        const auto part = MDE_G(double, S.partial);
+        for (int sl = s0; sl < s1; ++sl) {
+            double v[NSUM];
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) v[q] = part[((size_t)sl * WT + l) * NSUM + q];
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) sum[q] += v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NSUM; ++q) sum_s[q][l] = sum[q];
+    }
+    if (live)
+        for (int p = g; p < no; p += NG) I.newrow[(size_t)w * I.nomax + p] = orb[p];
+    __syncthreads();
+    if (g != 0 || !live) return;
+    // c and r = a'^T A^-1 - e_i^T for the commit (tiled like the tables)
+    for (int j = 0; j < n; ++j) {
+        double r = 0.0;
+#pragma unroll
+        for (int h = 0; h < NG; ++h) r += rr_s[h][j][l];
+        MDE_GW(double, I.rrow)[((size_t)t * n + j) * WT + l] = r - (j == row ? 1.0 : 0.0);
+        MDE_GW(double, I.cc)[((size_t)t * n + j) * WT + l] = c_s[j][l];
+    }
+    double rk[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        double v = 0.0;
+        for (int r = 0; r < n; ++r) v = fma(o_s[b][r][l], c_s[r][l], v);
+        rk[b] = v;
+    }
+    I.rho[w] = rk[0];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) I.kap[(size_t)w * 4 + b] = rk[1 + b];
+    const int bits = (!isfinite(rk[0]) || fabs(rk[0]) < 1e-300) ? 2 : 0;
+    I.st[w] = (I.st[w] & ~2) | bits;
+    double sum[NSUM];
+#pragma unroll
+    for (int q = 0; q < NSUM; ++q) sum[q] = sum_s[q][l];
+    finish_walker(I, mv, w, sum);
+}
+
+hipError_t launch_post(hipStream_t st, const InstDev *d_inst, const MoveArgs &m1, int n_tiles,
+                       int n_max) {
+    if (n_max > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_post, dim3(n_tiles), dim3(256), 0, st, d_inst, m1);
     return hipGetLastError();
 }
 

@@ -600,7 +600,29 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
     }
     const size_t tb = (size_t)t * nm * WT;
     const int ec = (nm * WT + split - 1) / split, e0 = part * ec, e1 = min(nm * WT, e0 + ec);
-    if (I.prec == 0) {
+    if (I.prec == 0 && (mv.mode & MV_FUSED)) {
+        // the part owns the virtual columns [p0, p1) of every row: it forms
+        // q_p = a'^T T[:, p] - phi'_p from the old table, then updates them
+        const int mc = (m + split - 1) / split, p0 = min(m, part * mc), p1 = min(m, p0 + mc);
+        double *q_s = rr_s + n * WT;      // [mc][WT]
+        for (int idx = tid; idx < (p1 - p0) * WT; idx += nthr) {
+            const int pl = idx / WT, l = idx - pl * WT, p = p0 + pl;
+            double q = 0.0;
+            if (l < nw) {
+                const auto a = MDE_G(double, I.newrow) + (size_t)(w0 + l) * I.nomax;
+                for (int r = 0; r < n; ++r) q = fma(a[r], S.T[tb + (size_t)(r * m + p) * WT + l], q);
+                q -= a[n + p];
+            }
+            q_s[idx] = q;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < n * (p1 - p0) * WT; idx += nthr) {
+            const int l = idx % WT, e = idx / WT, r = e / (p1 - p0), pl = e - r * (p1 - p0);
+            if (!acc_s[l]) continue;
+            const size_t o = tb + (size_t)(r * m + p0 + pl) * WT + l;
+            S.T[o] = fma(-cp_s[r * WT + l], q_s[pl * WT + l], S.T[o]);
+        }
+    } else if (I.prec == 0) {
         const auto qv = MDE_G(double, I.ev) + (size_t)t * 5 * m * WT;
         int idx = e0 + tid;
         // four entries per thread in flight
@@ -665,7 +687,7 @@ hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int
                          int mmax, int WT, int max_tiles, int split) {
     const int T8 = (max_tiles + NXCD - 1) / NXCD * NXCD;
     dim3 g(n_inst * T8 * split);
-    const size_t lds = sizeof(double) * 2 * (size_t)nmax * WT;
+    const size_t lds = sizeof(double) * (2 * (size_t)nmax + (mmax + split - 1) / split) * WT;
 #define MDE_AC(X)                                                                              \
     case X:                                                                                    \
         hipLaunchKernelGGL(k_accept<X>, g, dim3(256), lds, st, d_insts, d_moves, m1, split,   \
@@ -676,7 +698,7 @@ hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int
         default: return hipErrorInvalidValue;
     }
 #undef MDE_AC
-    (void)prec; (void)maxW; (void)mmax;
+    (void)prec; (void)maxW;
     return hipGetLastError();
 }
 

@@ -106,6 +106,7 @@ struct mde_ctx {
     bool R_valid[2] = {false, false};
     bool C_valid[2] = {false, false};
     int pending_e = -1;
+    bool pending_fused = false;   // the pending proposal was formed in the determinant kernel
     long accept_count = 0;
     bool capturing = false;
     const double *last_T[2] = {nullptr, nullptr};   // tables of the last mde_eval_tables
@@ -243,7 +244,7 @@ static size_t det_lds(const SpinHost &s, int WT, int threads, int prec, bool pro
         // c rows, then each wave's FP64 particle weights; the end-of-item
         // reduction reuses the space
         if (propose) {
-            tab += (size_t)s.n * WTP * esz + (size_t)(threads / 64) * s.m * 64 * 8;
+            tab += (size_t)s.n * WTP * esz + (size_t)(threads / 64) * s.m * 64 * 8 + (size_t)s.n * 64 * 8;
             red = (size_t)(threads / 64) * 64 * (NSUM + NE) * 8;
         }
     } else if (propose) {
@@ -433,6 +434,9 @@ static ItemQueues build_items(const SpinHost &s, int W, int WT, int item_exc, in
                 it.d0 = us[dcut[i]];
                 it.d1 = us[dcut[i + 1]];
                 if (it.u1 <= it.u0 && it.d1 <= it.d0) continue;
+                // the tile's first item also forms the move's quantities
+                // when the proposal is fused into the determinant kernel
+                it.order = (int)per.size() == tile_slot[t] ? 1 : 0;
                 it.slot = (int)per.size();
                 it.wb = -1;
                 if (bounds) {
@@ -1233,11 +1237,18 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
     m.lap = lap;
     m.status = status;
     const int nmax = c->h.nmax, mmax = c->h.mmax;
-    const int split = prop_split(c->n_cu, c->h.s[s].n_tiles, nmax, mmax, c->WT);
-    if (split == 0) MDE_FAIL(c, MDE_UNSUPPORTED, "proposal does not fit in LDS");
-    MDE_HIP(c, launch_propose(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, nmax, mmax,
-                              c->WT, c->h.s[s].n_tiles, split));
     SpinHost &sp = c->sp[s];
+    // FP64 on 64-walker tiles (at most 8 electrons per spin): the
+    // determinant kernel forms the proposal, k_post the commit's quantities
+    const bool fused = c->d.precision == 0 && c->WT == 64 && !sp.items.empty() && sp.n <= 8;
+    if (fused) {
+        m.mode |= MV_FUSED;
+    } else {
+        const int split = prop_split(c->n_cu, c->h.s[s].n_tiles, nmax, mmax, c->WT);
+        if (split == 0) MDE_FAIL(c, MDE_UNSUPPORTED, "proposal does not fit in LDS");
+        MDE_HIP(c, launch_propose(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, nmax,
+                                  mmax, c->WT, c->h.s[s].n_tiles, split));
+    }
     const bool prof = c->prof_on && 2 * (c->prof_used + 1) <= (int)c->prof_ev.size();
     if (prof) MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream));
     if (!sp.items.empty())
@@ -1248,8 +1259,12 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
         MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream));
         c->prof_used++;
     }
-    MDE_HIP(c, launch_finish(c->stream, c->d_inst, 1, c->W, nullptr, m, c->h.counter));
+    if (fused)
+        MDE_HIP(c, launch_post(c->stream, c->d_inst, m, c->h.s[s].n_tiles, sp.n));
+    else
+        MDE_HIP(c, launch_finish(c->stream, c->d_inst, 1, c->W, nullptr, m, c->h.counter));
     c->pending_e = e;
+    c->pending_fused = fused;
     return MDE_OK;
 }
 
@@ -1275,6 +1290,7 @@ mde_status mde_accept(mde_ctx *c, int32_t e, const uint8_t *accept) {
     m.spin = s;
     m.row = row;
     m.accept = accept;
+    if (c->pending_fused) m.mode |= MV_FUSED;
     MDE_HIP(c, launch_accept(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, c->h.nmax,
                              c->h.mmax, c->WT, c->h.s[s].n_tiles,
                              row_split(c->n_cu, c->h.s[s].n_tiles, c->sp[s].n)));
@@ -1850,7 +1866,10 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const
         MDE_GFAIL(g, MDE_DEVICE, "determinant launch");
     if (launch_finish(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, nullptr) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "finish launch");
-    for (int i = 0; i < n; ++i) g->ctx[i]->pending_e = e[i];
+    for (int i = 0; i < n; ++i) {
+        g->ctx[i]->pending_e = e[i];
+        g->ctx[i]->pending_fused = false;
+    }
     return MDE_OK;
 }
 

@@ -120,8 +120,12 @@ struct InstDev {
 };
 
 // Per-call move arguments (device array for groups, by value otherwise).
+// MoveArgs.mode bit: the determinant kernel forms the proposal quantities
+// itself (FP64 form on 64-walker tiles; no separate proposal launch)
+constexpr int32_t MV_FUSED = 1;
+
 struct MoveArgs {
-    int32_t e, spin, row, mode;   // electron, its spin, its row in A
+    int32_t e, spin, row, mode;   // electron, its spin, its row in A, MV_ bits
     const double *new_orb;        // [W][5][no]
     double *ratio, *grad, *lap;
     int32_t *status;
@@ -191,6 +195,8 @@ hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst,
                       const double *tab0, const double *tab1);
 // smallest part count of the proposal whose LDS footprint fits lds_max (0: none)
 int propose_split_limit(int nmax, int mmax, int WT, size_t lds_max);
+hipError_t launch_post(hipStream_t st, const InstDev *d_inst, const MoveArgs &m1, int n_tiles,
+                       int n_max);
 hipError_t launch_finish(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int32_t *counter);
 hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,

@@ -87,6 +87,10 @@ def _check(items, ranges, layout, s, spin, W, wt, threads):
         units = set(starts + [db])
     for t in range(n_tiles):
         mine = items[items[:, 2] == t]
+        if wt == 64:
+            # exactly one item of the tile (its first slot) forms the move's quantities
+            assert (mine[:, 3] == 1).sum() == 1
+            assert mine[mine[:, 3] == 1][0, 6] == mine[:, 6].min()
         cover = np.zeros(U, np.int32)
         for it in mine:
             u0, u1, slot, wb, d0, d1 = (int(x) for x in it[4:10])
