@@ -1270,8 +1270,18 @@ __global__ void __launch_bounds__(256) k_pc_fix(const InstDev *__restrict__ inst
     if (lg >= S.n_longs) return;
     const int4 L = S.longs[lg];
     double s = 0.0;
-    for (int p = L.y; p < L.z; ++p)
-        s += MDE_G(double, S.pc_part)[((size_t)p * S.n_tiles + t) * WT + wl];
+    const auto pp = MDE_G(double, S.pc_part) + (size_t)t * WT + wl;
+    const size_t ps = (size_t)S.n_tiles * WT;
+    int p = L.y;
+    // eight independent loads in flight, added in piece order
+    for (; p + 8 <= L.z; p += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = pp[(size_t)(p + k) * ps];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; p < L.z; ++p) s += pp[(size_t)p * ps];
     MDE_GW(double, S.C)[((size_t)t * S.U + L.x) * WT + wl] = s;
 }
 

@@ -682,6 +682,76 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
     }
 }
 
+// Commit of a proposal formed in the determinant kernel (FP64, 64-walker
+// tiles; Sherman-Morrison row update of Sec. III with the table update
+// T' = T - c' q^T, c' = c / rho): block (tile, part), part p owns the
+// virtual columns p, p + P, ... of every row (it forms q from the old
+// table, then updates those entries), the rows k = p, p + P, ... of each
+// walker's inverse, and a share of the orbital row; every load of a thread
+// is issued before its arithmetic.  Thread (g, l): walker lane l, group g.
+__global__ void __launch_bounds__(256)
+k_accept64f(const InstDev *__restrict__ insts, MoveArgs mv, int split, int T8) {
+    constexpr int WT = 64, NMAX = 8, NG = 4;
+    int inst, t, part;
+    if (!tile_of_block(split, T8, 1, inst, t, part)) return;
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[mv.spin];
+    if (t >= S.n_tiles) return;
+    const int n = S.n, m = S.m, no = S.no, nm = n * m, nn = n * n, row = mv.row, W = I.W;
+    const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int w = t * WT + l;
+    if (w >= W || !mv.accept[w]) return;
+    const double rho = I.rho[w];
+    const double ir = 1.0 / rho;
+    double cp[NMAX], a[NMAX];
+    const auto cc = MDE_G(double, I.cc) + (size_t)t * n * WT + l;
+    const auto nr = MDE_G(double, I.newrow) + (size_t)w * I.nomax;
+#pragma unroll
+    for (int r = 0; r < NMAX; ++r) {
+        cp[r] = r < n ? cc[(size_t)r * WT] * ir : 0.0;
+        a[r] = r < n ? nr[r] : 0.0;
+    }
+    // columns p = part + P * (g + NG * i): q from the old table, then update
+    double *T = S.T + (size_t)t * nm * WT + l;
+    for (int p = part + split * g; p < m; p += split * NG) {
+        double tv[NMAX];
+#pragma unroll
+        for (int r = 0; r < NMAX; ++r) tv[r] = r < n ? T[(size_t)(r * m + p) * WT] : 0.0;
+        double q = -nr[n + p];
+#pragma unroll
+        for (int r = 0; r < NMAX; ++r) q = fma(a[r], tv[r], q);
+#pragma unroll
+        for (int r = 0; r < NMAX; ++r)
+            if (r < n) T[(size_t)(r * m + p) * WT] = fma(-cp[r], q, tv[r]);
+    }
+    // rows k = part + P * i of the inverse: B[k][j] -= c'_k r_j
+    const auto rr = MDE_G(double, I.rrow) + (size_t)t * n * WT + l;
+    double *B = S.B + (size_t)w * nn;
+    for (int k = part; k < n; k += split) {
+        double ck = 0.0;
+#pragma unroll
+        for (int r = 0; r < NMAX; ++r)
+            if (r == k) ck = cp[r];
+        for (int j = g; j < n; j += NG) B[k * n + j] = fma(-ck, rr[(size_t)j * WT], B[k * n + j]);
+    }
+    // orbital row of the moved electron
+    double *Phi = S.Phi + ((size_t)w * n + row) * no;
+    for (int p = part * NG + g; p < no; p += split * NG) Phi[p] = nr[p];
+    if (part == 0 && g == 0) {
+        S.logdet[w] += log(fabs(rho));
+        if (rho < 0.0) S.sgn[w] = -S.sgn[w];
+        I.Nold[w] = I.Nnew[w];
+    }
+}
+
+hipError_t launch_accept64f(hipStream_t st, const InstDev *d_inst, const MoveArgs &m1, int n_tiles,
+                            int split, int n_max) {
+    if (n_max > 8) return hipErrorInvalidValue;
+    const int T8 = (n_tiles + NXCD - 1) / NXCD * NXCD;
+    hipLaunchKernelGGL(k_accept64f, dim3(T8 * split), dim3(256), 0, st, d_inst, m1, split, T8);
+    return hipGetLastError();
+}
+
 hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
                          int mmax, int WT, int max_tiles, int split) {

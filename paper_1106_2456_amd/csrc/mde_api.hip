@@ -1290,10 +1290,15 @@ mde_status mde_accept(mde_ctx *c, int32_t e, const uint8_t *accept) {
     m.spin = s;
     m.row = row;
     m.accept = accept;
-    if (c->pending_fused) m.mode |= MV_FUSED;
-    MDE_HIP(c, launch_accept(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, c->h.nmax,
-                             c->h.mmax, c->WT, c->h.s[s].n_tiles,
-                             row_split(c->n_cu, c->h.s[s].n_tiles, c->sp[s].n)));
+    if (c->pending_fused) {
+        m.mode |= MV_FUSED;
+        MDE_HIP(c, launch_accept64f(c->stream, c->d_inst, m, c->h.s[s].n_tiles,
+                                    row_split(c->n_cu, c->h.s[s].n_tiles, c->sp[s].n), c->sp[s].n));
+    } else {
+        MDE_HIP(c, launch_accept(c->stream, c->d_inst, 1, c->W, nullptr, m, c->d.precision, c->h.nmax,
+                                 c->h.mmax, c->WT, c->h.s[s].n_tiles,
+                                 row_split(c->n_cu, c->h.s[s].n_tiles, c->sp[s].n)));
+    }
     c->R_valid[s] = false;
     c->C_valid[1 - s] = false;
     c->pending_e = -1;

@@ -199,6 +199,8 @@ hipError_t launch_post(hipStream_t st, const InstDev *d_inst, const MoveArgs &m1
                        int n_max);
 hipError_t launch_finish(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int32_t *counter);
+hipError_t launch_accept64f(hipStream_t st, const InstDev *d_inst, const MoveArgs &m1, int n_tiles,
+                            int split, int n_max);
 hipError_t launch_accept(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                          const MoveArgs *d_moves, const MoveArgs &m1, int prec,
                          int nmax, int mmax, int WT, int max_tiles, int split);
