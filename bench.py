@@ -55,11 +55,45 @@ def flops_per_launch(exc, W: int) -> float:
 def bytes_per_launch(exc, W: int, n: int, m: int, precision: str) -> float:
     """Algorithmic HBM bytes of one determinant-kernel launch: each walker's CI
     weight C_u of every excitation of the moving spin (8 B, read once), the
-    walker's tables once (FP64 form: T [n*m], q and w^a [5m], c [n]; mixed
-    forms: FP32 T' [n*m], g^a [4m], c' [n]) and its five output sums."""
+    walker's inputs once and its output sums once.  FP64 form (the kernel
+    forms the proposal itself): T [n*m], the inverse [n*n], the new orbital
+    values and their gradient and laplacian [5(n+m)], six sums out.  Mixed
+    forms: FP32 T' [n*m], g^a [4m], c' [n], five sums out."""
     U = int((exc.orders() > 0).sum())
-    tab = 8 * (n * m + 5 * m + n) if precision == "fp64" else 4 * (n * m + 4 * m + n)
-    return float(W) * (8 * U + tab + 5 * 8)
+    if precision == "fp64":
+        return float(W) * (8 * U + 8 * (n * m + n * n + 5 * (n + m)) + 6 * 8)
+    return float(W) * (8 * U + 4 * (n * m + 4 * m + n) + 5 * 8)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_det_propose_water_batched_traffic.md")
+KERNEL_SOURCES = ("paper_1106_2456_amd/csrc/k_dets.hip", "paper_1106_2456_amd/csrc/mde_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(plan):
+    """HBM bytes per launch of the determinant kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter
+    on a copy of known size), or None when the kernel sources or the plan
+    have changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if line.startswith("traffic_"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("traffic_source_hash") != kernel_source_hash():
+        return None
+    if kv.get("traffic_plan") != json.dumps(plan, sort_keys=True):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -79,7 +113,7 @@ def build_context(wl, precision, stream, refresh_every):
     return ctx
 
 
-def run_form(wl, precision, steps, warmup, autotune=True):
+def run_form(wl, precision, steps, warmup, autotune=True, repeat=8):
     """Time `steps` sweeps (one graph) of one precision form; returns a dict."""
     import torch
     s = wl.system
@@ -136,10 +170,7 @@ def run_form(wl, precision, steps, warmup, autotune=True):
         stream.synchronize()
         torch.cuda.synchronize()
         ms_total = t0.elapsed_time(t1)
-        # the same K sweeps once more, issued directly, with a HIP event pair
-        # around every launch of the determinant kernel (events recorded
-        # inside a graph carry no timestamps on this runtime)
-        ctx.profile_enable(steps * n_tot)
+        # the same K sweeps issued directly (no graph)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -148,8 +179,21 @@ def run_form(wl, precision, steps, warmup, autotune=True):
         e1.record(stream)
         stream.synchronize()
         ms_eager = e0.elapsed_time(e1)
-        det_ms, det_n = ctx.profile_read()
-        ctx.profile_disable()
+        # K more sweeps with a HIP event pair on the context's stream around
+        # every launch of the determinant kernel (events recorded inside a
+        # graph carry no timestamps on this runtime): once with one launch
+        # per pair, once with `repeat` back-to-back launches per pair, which
+        # spreads the dispatch gap after the first event over the repeats
+        det = {}
+        for rep in (1, repeat):
+            ctx.profile_enable(steps * n_tot, rep)
+            for _ in range(steps):
+                sweep()
+            stream.synchronize()
+            det[rep] = ctx.profile_read()
+            ctx.profile_disable()
+        det_ms, det_n = det[repeat]
+        single_ms, single_n = det[1]
         st = torch.stack([o[3] for o in outs]).cpu().numpy()
     ms_step = ms_total / steps
     wdets = W * s.n_det * n_tot
@@ -160,6 +204,7 @@ def run_form(wl, precision, steps, warmup, autotune=True):
     return dict(precision=precision, ms_per_step=ms_step, value=wdets / (ms_step / 1e3),
                 ms_per_step_eager=ms_eager / steps,
                 det_launches=det_n, det_avg_us=det_avg_s * 1e6, det_flops_per_launch=fl,
+                det_single_us=single_ms / max(single_n, 1) * 1e3, det_repeat=repeat,
                 det_bytes_per_launch=by,
                 det_gbs=by / det_avg_s / 1e9 if det_n else None,
                 det_tflops=fl / det_avg_s / 1e12 if det_n else None, plan=plan,
@@ -172,17 +217,22 @@ def cpu_baseline(wl, target_seconds=12.0):
     import oracle
     s = wl.system
     threads = oracle.num_threads()
-    sample_w = min(wl.walkers.W, max(64, 32 * threads))
-    pos = wl.walkers.pos[:sample_w].copy()
     n_tot = sum(s.n_elec)
+    # size the walker sample so that one sweep takes about target_seconds
+    probe = min(wl.walkers.W, 64)
+    t0 = time.perf_counter()
+    e = int(wl.moves.electron[0])
+    oracle.move(s, wl.walkers.pos[:probe].copy(), e, wl.walkers.pos[:probe, e] + wl.moves.disp[0, :probe])
+    per_walker_move = (time.perf_counter() - t0) / probe
+    sample_w = int(min(wl.walkers.W, max(probe, target_seconds / (n_tot * per_walker_move))))
+    pos = wl.walkers.pos[:sample_w].copy()
     moves = 0
     t0 = time.perf_counter()
-    while True:
-        k = moves % n_tot
+    for k in range(n_tot):
         e = int(wl.moves.electron[k])
         oracle.move(s, pos, e, pos[:, e] + wl.moves.disp[k, :sample_w])
         moves += 1
-        if time.perf_counter() - t0 > target_seconds or moves >= n_tot:
+        if time.perf_counter() - t0 > 3 * target_seconds:
             break
     dt = time.perf_counter() - t0
     walkers_done = moves * sample_w
@@ -201,6 +251,11 @@ def main():
     ap.add_argument("--walkers", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--repeat", type=int, default=8,
+                    help="back-to-back determinant-kernel launches per HIP event pair")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the forms, run a plain device copy (torch.neg, out=) of this many "
+                         "MiB three times: the known-size reference for the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the walkers are "
@@ -218,15 +273,23 @@ def main():
     log(f"workload: W={wl.walkers.W} n_det={wl.system.n_det} U={wl.meta['n_exc_up']}/{wl.meta['n_exc_dn']}")
     forms = {}
     for f in [x for x in args.forms.split(",") if x]:
-        r = run_form(wl, f, args.steps, args.warmup, autotune=not args.no_autotune)
+        r = run_form(wl, f, args.steps, args.warmup, autotune=not args.no_autotune, repeat=args.repeat)
         log(f"{f}: {r['ms_per_step']:.3f} ms/sweep  {r['value']:.3e} walker.det/s  "
-            f"det kernel {r['det_avg_us']:.1f} us ({r['det_gbs']:.0f} GB/s, {r['det_tflops']:.2f} TFLOP/s) "
-            f"plan {r['plan'][0]}")
+            f"det kernel {r['det_avg_us']:.1f} us ({r['det_gbs']:.0f} GB/s, {r['det_tflops']:.2f} TFLOP/s; "
+            f"{r['det_single_us']:.1f} us one launch per event pair) plan {r['plan'][0]}")
         forms[f] = r
+    if args.copy_mib > 0:
+        x = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log(f"copy reference: 3 x torch.neg over {args.copy_mib} MiB (read + write each)")
+        del x, y
     head = forms.get("fp64") or next(iter(forms.values()))
     cpu = None if args.no_cpu else cpu_baseline(wl)
     achieved = head["det_gbs"]
-    traffic = None
+    traffic = measured_traffic(head["plan"]) if head["precision"] == "fp64" else None
     out = {
         "metric": "excited-det ratios/s (walker.det, +grad/lap) mixed/batched vs plain FP64",
         "value": head["value"],
@@ -247,15 +310,19 @@ def main():
                    "moves_per_step": sum(wl.system.n_elec), "precision": head["precision"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic, "kernel": "k_det<double, propose>",
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE)",
+                     "kernel": "k_det<double, propose>",
                      "launch_us": head["det_avg_us"],
+                     "launch_us_one_per_event_pair": head["det_single_us"],
+                     "launches_per_event_pair": head["det_repeat"],
                      "bytes_per_launch": head["det_bytes_per_launch"],
                      "alu": {"achieved": head["det_tflops"], "peak": PEAK_FP64_VECTOR_TFLOPS,
                              "unit": "TFLOP/s", "frac": head["det_tflops"] / PEAK_FP64_VECTOR_TFLOPS,
                              "flops_per_launch": head["det_flops_per_launch"]}},
         "cpu_baseline": cpu,
         "forms": {k: {kk: v[kk] for kk in ("value", "ms_per_step", "ms_per_step_eager", "det_avg_us",
-                                           "det_gbs", "det_tflops", "status_bits", "plan")}
+                                           "det_single_us", "det_gbs", "det_tflops", "status_bits",
+                                           "plan")}
                   for k, v in forms.items()},
     }
     print(json.dumps(out))

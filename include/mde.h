@@ -236,14 +236,21 @@ mde_status mde_autotune(mde_ctx *ctx, const double *new_orb_up,
 /* ---- profiling ---------------------------------------------------------- */
 
 /* While enabled, every launch of the determinant kernel made by a proposal
- * (mde_propose / mde_grad_lap) is bracketed by a pair of HIP events recorded
- * on the context's stream -- inside captured graphs too, where each captured
- * launch gets its own pair.  At most max_launches pairs are recorded; later
- * launches are not bracketed.  Host-side objects only. */
-mde_status mde_profile_enable(mde_ctx *ctx, int32_t max_launches);
+ * (mde_propose / mde_grad_lap) is bracketed by a pair of HIP events recorded on the
+ * context's stream -- inside captured graphs too, where each captured launch
+ * gets its own pair.  With repeat > 1 (at most 64) the bracketed launch is
+ * issued repeat times back to back between its two events, so that the
+ * dispatch gap after the first event is spread over the repeats; in the
+ * proposal mode the kernel writes only its partial sums (and resets its own
+ * work queues), so the repeats leave the proposal's results unchanged.  At
+ * most max_launches pairs are recorded; later launches are neither bracketed
+ * nor repeated.  Host-side objects only; MDE_INVALID for a count out of
+ * range. */
+mde_status mde_profile_enable(mde_ctx *ctx, int32_t max_launches, int32_t repeat);
 /* After the caller has synchronised the stream: sum of the elapsed times of
- * the recorded pairs (ms) and their number.  Pairs captured into a graph
- * hold the times of that graph's last replay. */
+ * the recorded pairs (ms) and the number of kernel launches they hold
+ * (pairs x repeat).  Pairs captured into a graph hold the times of that
+ * graph's last replay. */
 mde_status mde_profile_read(mde_ctx *ctx, double *total_ms, int32_t *count);
 mde_status mde_profile_disable(mde_ctx *ctx);
 

@@ -56,7 +56,7 @@ _SIGS = {
     "mde_debug_items": ([_P, _I, _I, _I, _I, _I, _P, _I, C.POINTER(_I), _P, _I, C.POINTER(_I), _P],
                         C.c_int),
     "mde_autotune": ([_P, _P, _P, C.c_char_p], C.c_int),
-    "mde_profile_enable": ([_P, _I], C.c_int),
+    "mde_profile_enable": ([_P, _I, _I], C.c_int),
     "mde_profile_read": ([_P, C.POINTER(C.c_double), C.POINTER(_I)], C.c_int),
     "mde_profile_disable": ([_P], C.c_int),
     "mde_capture_begin": ([_P], C.c_int),

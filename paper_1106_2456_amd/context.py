@@ -247,8 +247,8 @@ class Context:
         cp = cache_path.encode() if cache_path else None
         self._chk(lib().mde_autotune(self._h, _ptr(new_orb_up), _ptr(new_orb_dn), cp), "autotune")
 
-    def profile_enable(self, max_launches: int):
-        self._chk(lib().mde_profile_enable(self._h, max_launches), "profile_enable")
+    def profile_enable(self, max_launches: int, repeat: int = 1):
+        self._chk(lib().mde_profile_enable(self._h, max_launches, repeat), "profile_enable")
 
     def profile_read(self):
         """(total ms, count) of the bracketed determinant-kernel launches."""

@@ -113,6 +113,7 @@ struct mde_ctx {
     // profiling event pairs around determinant-kernel launches
     std::vector<hipEvent_t> prof_ev;
     int prof_used = 0;
+    int prof_repeat = 1;
     bool prof_on = false;
     // plan fields chosen by the caller (kept when the default plan is applied)
     bool user_wt = false, user_thr[2] = {false, false}, user_item[2] = {false, false};
@@ -1251,7 +1252,11 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
     }
     const bool prof = c->prof_on && 2 * (c->prof_used + 1) <= (int)c->prof_ev.size();
     if (prof) MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream));
-    if (!sp.items.empty())
+    // a profiled launch is issued prof_repeat times back to back: in this mode
+    // the kernel writes only its partial sums and resets its own queues, so
+    // every repeat leaves the same result
+    const int reps = prof ? c->prof_repeat : 1;
+    for (int r = 0; r < reps && !sp.items.empty(); ++r)
         MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], c->d_bounds[s], sp.queues, sp.ex_cap,
                               nullptr, m, DM_PROPOSE, c->d.precision, c->WT, sp.lds_prop, sp.threads,
                               sp.grid, c->h.counter, nullptr, nullptr));
@@ -1551,14 +1556,16 @@ static void prof_free(mde_ctx *c) {
     c->prof_on = false;
 }
 
-mde_status mde_profile_enable(mde_ctx *c, int32_t max_launches) {
+mde_status mde_profile_enable(mde_ctx *c, int32_t max_launches, int32_t repeat) {
     if (!c) return MDE_INVALID;
     if (max_launches < 1 || max_launches > 1 << 16) MDE_FAIL(c, MDE_INVALID, "bad launch count");
+    if (repeat < 1 || repeat > 64) MDE_FAIL(c, MDE_INVALID, "bad repeat count");
     if (c->capturing) MDE_FAIL(c, MDE_STATE, "enable profiling before capture");
     prof_free(c);
     c->prof_ev.resize(2 * (size_t)max_launches);
     for (auto &e : c->prof_ev)
         MDE_HIP(c, hipEventCreate(&e));
+    c->prof_repeat = repeat;
     c->prof_on = true;
     return MDE_OK;
 }
@@ -1572,7 +1579,7 @@ mde_status mde_profile_read(mde_ctx *c, double *total_ms, int32_t *count) {
         t += ms;
     }
     *total_ms = t;
-    *count = c->prof_used;
+    *count = c->prof_used * c->prof_repeat;
     return MDE_OK;
 }
 

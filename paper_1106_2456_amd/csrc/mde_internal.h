@@ -77,12 +77,16 @@ __host__ __device__ constexpr bool dense_m_supported(int m) {
 // excitation's ring slot depends on its place in the pair only.  (The pair
 // body is straight-line code: one unit per pair keeps the ring in fixed
 // registers across pairs, with no wait for all loads at the loop edge.)
+// All five shapes live in one kernel, whose register budget (256 per lane
+// at 512 threads) is set by the deepest ring: rings of 20-38 doubles for
+// every shape spilled the item loop's state to scratch on each dense entry
+// (~20 MB of scratch write-back per launch); rings of 14-23 do not spill.
 template <int M>
 struct Dense2Shape {
     static constexpr int NP = M * (M - 1) / 2;
     static constexpr int G = 1;
     static constexpr int UNIT = NP / G;
-    static constexpr int PD = M == 8 ? 28 : M == 12 ? 33 : M == 16 ? 40 : M == 20 ? 38 : 46;
+    static constexpr int PD = M == 8 ? 14 : M == 12 ? 22 : M == 16 ? 20 : M == 20 ? 19 : 23;
     static_assert(NP % G == 0 && UNIT % PD == 0, "dense unit shape");
 };
 
