@@ -1382,11 +1382,11 @@ hipError_t launch_nsum(hipStream_t st, const InstDev *d_inst, const InstDev &h,
 //   ratio = rho N' / N_old,   grad^a = ((kappa^a / rho) N' + G^a) / N'.
 // ---------------------------------------------------------------------------
 
-// the walker's results from its summed partials (C_0 included in sum[0])
-__device__ __forceinline__ void finish_walker(const InstDev &I, const MoveArgs &mv, int w,
-                                              const double (&sum)[NSUM]) {
-    const double rho = I.rho[w];
-    const auto kap = MDE_G(double, I.kap) + (size_t)w * 4;
+// the walker's results from its summed partials (C_0 included in sum[0]),
+// its rho, kappa^a and status bits
+__device__ __forceinline__ void finish_walker_v(const InstDev &I, const MoveArgs &mv, int w,
+                                                const double (&sum)[NSUM], double rho,
+                                                const double (&kap)[4], int st) {
     double ratio, rNp, d[4];
     if (I.prec == 0) {
         const double N = sum[0];
@@ -1405,7 +1405,7 @@ __device__ __forceinline__ void finish_walker(const InstDev &I, const MoveArgs &
         for (int a = 0; a < 4; ++a) d[a] = fma(kap[a] * ir, Np, sum[1 + a]) * inv;
         I.Nnew[w] = Np;
     }
-    int bits = I.st[w] & 2;
+    int bits = st & 2;
     if (!(rNp != 0.0) || !isfinite(rNp)) bits |= 8;
     if (!isfinite(ratio) || !isfinite(d[0]) || !isfinite(d[1]) || !isfinite(d[2]) || !isfinite(d[3]))
         bits |= 4;
@@ -1417,6 +1417,13 @@ __device__ __forceinline__ void finish_walker(const InstDev &I, const MoveArgs &
     }
     if (mv.lap) mv.lap[w] = d[3];
     if (mv.status && bits) mv.status[w] |= bits;
+}
+
+__device__ __forceinline__ void finish_walker(const InstDev &I, const MoveArgs &mv, int w,
+                                              const double (&sum)[NSUM]) {
+    const auto kp = MDE_G(double, I.kap) + (size_t)w * 4;
+    const double kap[4] = {kp[0], kp[1], kp[2], kp[3]};
+    finish_walker_v(I, mv, w, sum, I.rho[w], kap, I.st[w]);
 }
 
 __global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves,
@@ -1523,18 +1530,29 @@ __global__ void __launch_bounds__(256) k_post(const InstDev *__restrict__ insts,
         double sum[NSUM] = {C0, 0.0, 0.0, 0.0, 0.0, 0.0};
         const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
         const auto part = MDE_G(double, S.partial);
-        for (int sl = s0; sl < s1; ++sl) {
-            double v[NSUM];
+        // slots in order; the loads of four slots are issued before they are added
+        int sl = s0;
+        for (; sl + 4 <= s1; sl += 4) {
+            double v[4][NSUM];
 #pragma unroll
-            for (int q = 0; q < NSUM; ++q) v[q] = part[((size_t)sl * WT + l) * NSUM + q];
+            for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int q = 0; q < NSUM; ++q) sum[q] += v[q];
+                for (int q = 0; q < NSUM; ++q) v[k][q] = part[((size_t)(sl + k) * WT + l) * NSUM + q];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int q = 0; q < NSUM; ++q) sum[q] += v[k][q];
+        }
+        for (; sl < s1; ++sl) {
+#pragma unroll
+            for (int q = 0; q < NSUM; ++q) sum[q] += part[((size_t)sl * WT + l) * NSUM + q];
         }
 #pragma unroll
         for (int q = 0; q < NSUM; ++q) sum_s[q][l] = sum[q];
     }
     if (live)
         for (int p = g; p < no; p += NG) I.newrow[(size_t)w * I.nomax + p] = orb[p];
+    const int st_old = (g == 0 && live) ? I.st[w] : 0;
     __syncthreads();
     if (g != 0 || !live) return;
     // c and r = a'^T A^-1 - e_i^T for the commit (tiled like the tables)
@@ -1556,11 +1574,13 @@ __global__ void __launch_bounds__(256) k_post(const InstDev *__restrict__ insts,
 #pragma unroll
     for (int b = 0; b < 4; ++b) I.kap[(size_t)w * 4 + b] = rk[1 + b];
     const int bits = (!isfinite(rk[0]) || fabs(rk[0]) < 1e-300) ? 2 : 0;
-    I.st[w] = (I.st[w] & ~2) | bits;
+    const int st = (st_old & ~2) | bits;
+    I.st[w] = st;
     double sum[NSUM];
 #pragma unroll
     for (int q = 0; q < NSUM; ++q) sum[q] = sum_s[q][l];
-    finish_walker(I, mv, w, sum);
+    const double kap[4] = {rk[1], rk[2], rk[3], rk[4]};
+    finish_walker_v(I, mv, w, sum, rk[0], kap, st);
 }
 
 hipError_t launch_post(hipStream_t st, const InstDev *d_inst, const MoveArgs &m1, int n_tiles,
