@@ -170,7 +170,11 @@ mde_status mde_grad_lap(mde_ctx *ctx, int32_t e, const double *cur_orb,
 /* Commit the pending proposal of electron e for walkers with accept[w] != 0
  * (uint8 [W]): Sherman-Morrison update of A0^-1 (Sec. III SM eq.), table,
  * reference determinant and CI sum.  Every refresh_every calls the state is
- * recomputed from scratch (mde_refresh without outputs). */
+ * recomputed from scratch (mde_refresh without outputs); in the FP64
+ * precision that refresh rebuilds A0^-1, T and log|det A0| only and keeps
+ * the CI sum N of the moves (every FP64 proposal sums N over its own
+ * determinants), and the excited ratios and CI weights are formed when the
+ * next proposal or export needs them. */
 mde_status mde_accept(mde_ctx *ctx, int32_t e, const uint8_t *accept);
 
 /* Copy internal state for checks.  what: 0 = A0^-1 of spin s [W][n][n],

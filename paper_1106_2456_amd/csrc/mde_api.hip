@@ -818,9 +818,17 @@ static mde_status ensure_C(mde_ctx *c, int s) {
     return MDE_OK;
 }
 
-// from-scratch evaluation; orb_* NULL means "use the kept orbital values"
+// from-scratch evaluation; orb_* NULL means "use the kept orbital values".
+// Every evaluation ends in the same state -- current inverses and tables,
+// the down ratios and the up CI weights marked current, the up ratios and
+// the down weights marked stale -- so that a captured sequence that starts
+// after one evaluation and ends with another replays consistently.  With
+// need_n false (the periodic refresh inside a run of FP64 moves) N is not
+// re-summed: an FP64 proposal sums N over its own determinants, and the
+// up ratios, which only N would need, are formed when a down electron next
+// moves (they change with every accepted up move anyway).
 static mde_status full_eval(mde_ctx *c, const double *orb_up, const double *orb_dn,
-                            double *log_abs, double *sign, int32_t *status) {
+                            double *log_abs, double *sign, int32_t *status, bool need_n = true) {
     const double *orb[2] = {orb_up, orb_dn};
     MDE_HIP(c, launch_coef_gather(c->stream, c->d_inst, c->h, c->h.coef));
     for (int s = 0; s < 2; ++s) {
@@ -829,15 +837,15 @@ static mde_status full_eval(mde_ctx *c, const double *orb_up, const double *orb_
     }
     c->R_valid[0] = c->R_valid[1] = false;
     c->C_valid[0] = c->C_valid[1] = false;
-    for (int s = 0; s < 2; ++s) {
+    for (int s = need_n ? 0 : 1; s < 2; ++s) {
         mde_status st = run_values(c, s);
         if (st) return st;
     }
-    // N = sum_u C_up[u] R_up[u] needs the up weights; the down weights are
-    // formed when a down electron next moves
     mde_status st0 = ensure_C(c, 0);
     if (st0) return st0;
-    MDE_HIP(c, launch_nsum(c->stream, c->d_inst, c->h, log_abs, sign, status, 1));
+    // N = sum_u C_up[u] R_up[u]
+    if (need_n) MDE_HIP(c, launch_nsum(c->stream, c->d_inst, c->h, log_abs, sign, status, 1));
+    c->R_valid[0] = false;
     c->initialized = true;
     c->adjoint_state = false;
     c->pending_e = -1;
@@ -1309,7 +1317,7 @@ mde_status mde_accept(mde_ctx *c, int32_t e, const uint8_t *accept) {
     c->pending_e = -1;
     c->accept_count++;
     if (c->d.refresh_every > 0 && c->accept_count % c->d.refresh_every == 0)
-        return full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr);
+        return full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr, c->d.precision != 0);
     return MDE_OK;
 }
 
@@ -1916,7 +1924,8 @@ mde_status mde_group_accept(mde_group *g, const int32_t *e, const uint8_t *const
         c->pending_e = -1;
         c->accept_count++;
         if (c->d.refresh_every > 0 && c->accept_count % c->d.refresh_every == 0) {
-            mde_status r = full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr);
+            mde_status r = full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                     c->d.precision != 0);
             if (r) MDE_GFAIL(g, r, "instance %d refresh: %s", i, c->err.c_str());
         }
     }

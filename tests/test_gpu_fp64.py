@@ -108,6 +108,16 @@ def test_trajectory_batched_walkers_and_state():
             A = orb[w, :, 0, :n]
             assert np.abs(B[w] @ A - np.eye(n)).max() <= 1e-11 * np.linalg.cond(A)
             assert abs(ld[w] - np.linalg.slogdet(A)[1]) <= 1e-11 * np.linalg.cond(A)
+    # the CI sum N = Psi / (D0_up D0_dn): the periodic FP64 refreshes (after
+    # moves 10 and 20) keep the N of the moves instead of re-summing it
+    r = oracle.mds(wl.system, rou, rod)
+    scale = np.exp(r["shift"] - r["log0"][:, 0] - r["log0"][:, 1])
+    n_ref = r["psi"] * r["sign0"][:, 0] * r["sign0"][:, 1] * scale
+    n_abs = r["psi_abs"] * scale
+    n_gpu = ctx.export("N").cpu().numpy()
+    err = (np.abs(n_gpu - n_ref) / n_abs).max()
+    say(f"N after 25 moves: scaled error {err:.2e}")
+    assert err <= 1e-10
 
 
 def test_sizing_query_after_bind_keeps_state():
