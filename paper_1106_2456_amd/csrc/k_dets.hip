@@ -1181,54 +1181,61 @@ k_precontract(const InstDev *__restrict__ insts, int spin, int ublocks) {
     const auto Cw = MDE_GW(double, out);
     double s = 0.0;
     if (WT == 64) {
-        // One unit per wave.  The unit's terms (other-spin excitation and
-        // coefficient, at most 2 x 64) and segment ends are loaded into the
-        // lanes with one vector load each and read back by lane index, so no
-        // scalar load sits on the chain; the gathers go out 16 at a time.
-        const int lane = threadIdx.x & 63;
-        const int nk = k1 - k0;
-        const int o_a = lane < nk ? oth[k0 + lane] : 0;
-        const int o_b = 64 + lane < nk ? oth[k0 + 64 + lane] : 0;
-        const double c_a = lane < nk ? cf[k0 + lane] : 0.0;
-        const double c_b = 64 + lane < nk ? cf[k0 + 64 + lane] : 0.0;
-        // ends of the chunk's excitations (pieces: one segment ending at k1)
+        // One unit per wave, lanes = the tile's walkers.  The unit's terms
+        // (other-spin excitation, coefficient, segment end) are uniform and
+        // read-only: scalar loads, 16 terms at a time, with the 16 ratio
+        // gathers in flight together.  A short segment's last term carries
+        // its excitation, where the sum is written; excitations without
+        // terms keep the zero the array was cleared to.
+        const int kb = __builtin_amdgcn_readfirstlane(k0);
+        const int nk = __builtin_amdgcn_readfirstlane(k1) - kb;
+        const auto oth_k = MDE_K(int32_t, S.ci_other) + kb;
+        const auto end_k = MDE_K(int32_t, S.ci_end) + kb;
+        const auto cf_k = MDE_K(double, S.coef_s) + kb;
         const bool chunk = ostride != 0;
-        const int ne = u1 - u;
-        const int e_a = chunk ? (lane < ne ? seg[u + 1 + lane] : k1) : k1;
-        const int e_b = chunk ? (64 + lane < ne ? seg[u + 65 + lane] : k1) : k1;
-        auto lane_i = [](int v, int i) { return __builtin_amdgcn_readlane(v, i); };
-        auto lane_d = [](double v, int i) {
-            const long long b = __double_as_longlong(v);
-            const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), i);
-            const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
-            return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-        };
-        int e = 0;   // index of the current excitation within the unit
-        int kend_l = lane_i(e_a, 0);
+        // past nk the loads read the next unit's terms or the padding:
+        // valid indices, never used.  The next batch's gathers are issued
+        // before this batch is summed.
+        double r[16];
+        {
+            int oi[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) oi[i] = oth_k[i];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) r[i] = Ro[(size_t)oi[i] * WT];
+        }
         for (int tb = 0; tb < nk; tb += 16) {
-            double r[16];
+            int we[16];
+            double c[16], rn[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int kk = tb + i;
-                const int oi = kk < 64 ? lane_i(o_a, kk & 63) : lane_i(o_b, kk & 63);
-                r[i] = kk < nk ? Ro[(size_t)oi * WT] : 0.0;
+                we[i] = end_k[tb + i];
+                c[i] = cf_k[tb + i];
             }
+            if (tb + 16 < nk) {
+                int oi[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) oi[i] = oth_k[tb + 16 + i];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) rn[i] = Ro[(size_t)oi[i] * WT];
+            }
+            // keep those loads ahead of this batch's sums (an empty asm with
+            // a memory clobber emits nothing)
+            __asm__ volatile("" ::: "memory");
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int kk = tb + i;
-                if (kk < nk) {
-                    while (k0 + kk >= kend_l) {
-                        Cw[(size_t)(u + e) * ostride] = s;
+                if (tb + i < nk) {
+                    s = fma(c[i], r[i], s);
+                    if (chunk && we[i] >= 0) {
+                        Cw[(size_t)we[i] * WT] = s;
                         s = 0.0;
-                        ++e;
-                        kend_l = e < 64 ? lane_i(e_a, e) : lane_i(e_b, e - 64);
                     }
-                    const double c = kk < 64 ? lane_d(c_a, kk & 63) : lane_d(c_b, kk & 63);
-                    s = fma(c, r[i], s);
                 }
             }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) r[i] = rn[i];
         }
-        u += e;
+        if (chunk) u = u1;
     } else
     for (int k = k0; k < k1; k += 8) {
         int o[8];

@@ -40,7 +40,7 @@ struct SpinHost {
     std::vector<uint4> ex;       // packed records, internal order
     std::vector<int> orders;     // order of each internal excitation
     int order_start[MAXK + 2] = {0};
-    std::vector<int> ci_seg, ci_other, ci_idx;
+    std::vector<int> ci_seg, ci_other, ci_end, ci_idx;
     std::vector<int> chunks;     // precontraction chunks (excitation boundaries)
     std::vector<int4> pieces;    // pieces of long CI segments (u, k0, k1, 0)
     std::vector<int4> longs;     // (u, first piece, end piece, 0)
@@ -641,7 +641,8 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
         SpinDev &S = h.s[s];
         S.ex = cv.take<uint4>(sp.U);
         S.ci_seg = cv.take<int32_t>(sp.U + 1);
-        S.ci_other = cv.take<int32_t>(c->n_det);
+        S.ci_other = cv.take<int32_t>(c->n_det + 16);
+        S.ci_end = cv.take<int32_t>(c->n_det + 16);
         S.ci_idx = cv.take<int32_t>(c->n_det);
         S.inv_off = cv.take<int32_t>((size_t)sp.n * sp.m + 1);
         S.inv_ent = cv.take<int32_t>(sp.inv_ent.size());
@@ -659,7 +660,7 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
         S.R = cv.take<double>(Wp * sp.U);
         S.C = cv.take<double>(Wp * sp.U);
         S.partial = cv.take<double>(max_partial[s]);
-        S.coef_s = cv.take<double>(c->n_det);
+        S.coef_s = cv.take<double>(c->n_det + 16);
         S.chunks = cv.take<int32_t>(sp.chunks.size());
         S.pieces = cv.take<int4>(sp.pieces.size());
         S.longs = cv.take<int4>(sp.longs.size());
@@ -716,6 +717,16 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
     }
     if (max_items_out) *max_items_out = max_items[0] + max_items[1];
     return cv.off;
+}
+
+// CI weights of excitations without CI terms are never written by the
+// precontraction: the whole array starts at zero whenever its tile layout
+// is (re)established
+static mde_status zero_weights(mde_ctx *c) {
+    const size_t Wp = (size_t)c->W + 64;
+    for (int s = 0; s < 2; ++s)
+        MDE_HIP(c, hipMemsetAsync(c->h.s[s].C, 0, sizeof(double) * Wp * c->sp[s].U, c->stream));
+    return MDE_OK;
 }
 
 // apply the context's plan: items, slots, LDS sizes, grids (host + upload)
@@ -1105,6 +1116,14 @@ mde_status mde_set_ci(mde_ctx *c, int64_t n_det, const double *coef, const int32
             }
         }
         if (cur < sp.U) { starts.push_back(cur); ends.push_back(sp.U); }
+        // the last term of every short segment names its excitation; the
+        // term arrays carry 16 entries of padding (read, never used)
+        sp.ci_end.assign(n_det + 16, -1);
+        for (int u = 0; u < sp.U; ++u) {
+            const int len = sp.ci_seg[u + 1] - sp.ci_seg[u];
+            if (len > 0 && len <= PIECE) sp.ci_end[sp.ci_seg[u + 1] - 1] = u;
+        }
+        sp.ci_other.resize(n_det + 16, 0);
         // chunks as (start, end) pairs flattened: chunks[2c], chunks[2c+1]
         sp.chunks.clear();
         for (size_t i = 0; i < starts.size(); ++i) {
@@ -1169,8 +1188,11 @@ mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
         MDE_HIP(c, hipMemcpy((void *)S.ex, sp.ex.data(), sizeof(uint4) * sp.U, hipMemcpyHostToDevice));
         MDE_HIP(c, hipMemcpy((void *)S.ci_seg, sp.ci_seg.data(), sizeof(int) * (sp.U + 1),
                              hipMemcpyHostToDevice));
-        MDE_HIP(c, hipMemcpy((void *)S.ci_other, sp.ci_other.data(), sizeof(int) * c->n_det,
+        MDE_HIP(c, hipMemcpy((void *)S.ci_other, sp.ci_other.data(), sizeof(int) * (c->n_det + 16),
                              hipMemcpyHostToDevice));
+        MDE_HIP(c, hipMemcpy((void *)S.ci_end, sp.ci_end.data(), sizeof(int) * (c->n_det + 16),
+                             hipMemcpyHostToDevice));
+        MDE_HIP(c, hipMemset(S.coef_s + c->n_det, 0, sizeof(double) * 16));
         MDE_HIP(c, hipMemcpy((void *)S.ci_idx, sp.ci_idx.data(), sizeof(int) * c->n_det,
                              hipMemcpyHostToDevice));
         MDE_HIP(c, hipMemcpy((void *)S.chunks, sp.chunks.data(), sizeof(int) * sp.chunks.size(),
@@ -1206,6 +1228,7 @@ mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
     mde_status st = apply_plan(c);
     if (st) return st;
     MDE_HIP(c, launch_init_misc(c->stream, c->d_inst, c->h));
+    if (mde_status zs = zero_weights(c)) return zs;
     MDE_HIP(c, hipStreamSynchronize(c->stream));
     return MDE_OK;
 }
@@ -1411,6 +1434,7 @@ mde_status mde_set_plan(mde_ctx *c, int32_t spin, int32_t walker_tile, int32_t i
     if (st) return st;
     c->initialized = false;   // R and C layouts depend on the tile: re-init needed
     MDE_HIP(c, launch_init_misc(c->stream, c->d_inst, c->h));
+    if (mde_status zs = zero_weights(c)) return zs;
     return MDE_OK;
 }
 
@@ -1468,6 +1492,7 @@ static mde_status replan_keep_state(mde_ctx *c, const Plan &p) {
     mde_status st = apply_plan(c);
     if (st) return st;
     MDE_HIP(c, launch_init_misc(c->stream, c->d_inst, c->h));
+    if (mde_status zs = zero_weights(c)) return zs;
     return full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 

@@ -38,7 +38,9 @@ struct SpinDev {
     int32_t dense_k;
     const uint4 *ex;          // [U] packed: bytes 0..7 holes, 8..15 particles - n
     const int32_t *ci_seg;    // [U+1] CI terms of this spin's excitation u
-    const int32_t *ci_other;  // [n_det] other spin's excitation, per term
+    const int32_t *ci_other;  // [n_det + 16] other spin's excitation, per term (0 past the end)
+    const int32_t *ci_end;    // [n_det + 16] u when the term is the last of u's short CI
+                              // segment, else -1
     const int32_t *ci_idx;    // [n_det] original determinant index, per term
     const int32_t *inv_off;   // [n*m+1] adjoint inverted index by entry
     const int32_t *inv_ent;   // packed (u << 6) | (j << 3) | l
@@ -56,7 +58,7 @@ struct SpinDev {
     double *R;       // [n_tiles][U][WT] excited ratios at current positions
     double *C;       // [n_tiles][U][WT] CI weights: sum over terms of c_I R_other
     double *partial; // [n_slots][WT][NSUM]
-    double *coef_s;  // [n_det] c_I in this spin's CI-term order
+    double *coef_s;  // [n_det + 16] c_I in this spin's CI-term order
     const int32_t *chunks;   // [2*n_chunks] (first, end) excitation ranges of the precontraction
     const int4 *pieces;      // [n_pieces] (u, k0, k1, -) pieces of long CI segments
     const int4 *longs;       // [n_longs] (u, first piece, end piece, -)
@@ -142,6 +144,9 @@ enum DetMode { DM_PROPOSE = 0, DM_VALUES = 1 };
 // make their loads global-memory loads (no LDS counter involvement).
 #define MDE_G(T, p) ((const T __attribute__((address_space(1))) *)(p))
 #define MDE_GW(T, p) ((T __attribute__((address_space(1))) *)(p))
+// read-only for the whole launch (set up on the host): uniform reads become
+// scalar loads
+#define MDE_K(T, p) ((const T __attribute__((address_space(4))) *)(p))
 
 // Largest excitation range of one work item (its records are staged in LDS).
 constexpr int ITEM_MAX = 1024;
