@@ -1444,7 +1444,9 @@ __global__ void k_finish(const InstDev *__restrict__ insts, const MoveArgs *__re
     const int WT = S.WT, t = w / WT, wl = w - t * WT;
     const double C0 = MDE_G(double, S.C)[(size_t)t * S.U * WT + wl];
     double sum[NSUM] = {C0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
+    const int spt = S.slots_per_tile;
+    const int s0 = spt > 0 ? t * spt : MDE_G(int32_t, S.tile_slot)[t];
+    const int s1 = spt > 0 ? s0 + spt : MDE_G(int32_t, S.tile_slot)[t + 1];
     const auto part = MDE_G(double, S.partial);
     // slots in order; the loads of four slots are issued before they are added
     int s = s0;
@@ -1535,7 +1537,9 @@ __global__ void __launch_bounds__(256) k_post(const InstDev *__restrict__ insts,
     if (g == 1 && live) {
         const double C0 = MDE_G(double, S.C)[(size_t)t * S.U * WT + l];
         double sum[NSUM] = {C0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        const int s0 = MDE_G(int32_t, S.tile_slot)[t], s1 = MDE_G(int32_t, S.tile_slot)[t + 1];
+        const int spt = S.slots_per_tile;
+        const int s0 = spt > 0 ? t * spt : MDE_G(int32_t, S.tile_slot)[t];
+        const int s1 = spt > 0 ? s0 + spt : MDE_G(int32_t, S.tile_slot)[t + 1];
         const auto part = MDE_G(double, S.partial);
         // slots in order; the loads of four slots are issued before they are added
         int sl = s0;

@@ -700,24 +700,62 @@ k_accept64f(const InstDev *__restrict__ insts, MoveArgs mv, int split, int T8) {
     const int n = S.n, m = S.m, no = S.no, nm = n * m, nn = n * n, row = mv.row, W = I.W;
     const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int w = t * WT + l;
-    if (w >= W || !mv.accept[w]) return;
+    if (w >= W) return;
+    // the walker's inputs are loaded together with its accept flag (all
+    // addresses are valid either way); a rejected walker drops them
+    const bool acc = mv.accept[w] != 0;
     const double rho = I.rho[w];
-    const double ir = 1.0 / rho;
     double cp[NMAX], a[NMAX];
     const auto cc = MDE_G(double, I.cc) + (size_t)t * n * WT + l;
     const auto nr = MDE_G(double, I.newrow) + (size_t)w * I.nomax;
 #pragma unroll
     for (int r = 0; r < NMAX; ++r) {
-        cp[r] = r < n ? cc[(size_t)r * WT] * ir : 0.0;
+        cp[r] = r < n ? cc[(size_t)r * WT] : 0.0;
         a[r] = r < n ? nr[r] : 0.0;
     }
-    // columns p = part + P * (g + NG * i): q from the old table, then update
     double *T = S.T + (size_t)t * nm * WT + l;
-    for (int p = part + split * g; p < m; p += split * NG) {
-        double tv[NMAX];
+    const int p0 = part + split * g;
+    double tv0[NMAX], q0 = 0.0;
+    if (p0 < m) {
 #pragma unroll
-        for (int r = 0; r < NMAX; ++r) tv[r] = r < n ? T[(size_t)(r * m + p) * WT] : 0.0;
-        double q = -nr[n + p];
+        for (int r = 0; r < NMAX; ++r) tv0[r] = r < n ? T[(size_t)(r * m + p0) * WT] : 0.0;
+        q0 = -nr[n + p0];
+    }
+    // first row of the inverse this thread updates (k = part, j = g, g + NG)
+    // and its first orbital-row entry, also ahead of the flag
+    const auto rr = MDE_G(double, I.rrow) + (size_t)t * n * WT + l;
+    double *B = S.B + (size_t)w * nn;
+    double b0[2] = {0.0, 0.0}, r0[2] = {0.0, 0.0};
+    if (part < n) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = g + h * NG;
+            if (j < n) {
+                b0[h] = B[part * n + j];
+                r0[h] = rr[(size_t)j * WT];
+            }
+        }
+    }
+    const int pf = part * NG + g;
+    const double nf = pf < no ? nr[pf] : 0.0;
+    const double nnew = I.Nnew[w];
+    if (!acc) return;
+    const double ir = 1.0 / rho;
+#pragma unroll
+    for (int r = 0; r < NMAX; ++r) cp[r] *= ir;
+    // columns p = part + P * (g + NG * i): q from the old table, then update
+    for (int p = p0; p < m; p += split * NG) {
+        double tv[NMAX];
+        double q;
+        if (p == p0) {
+#pragma unroll
+            for (int r = 0; r < NMAX; ++r) tv[r] = tv0[r];
+            q = q0;
+        } else {
+#pragma unroll
+            for (int r = 0; r < NMAX; ++r) tv[r] = r < n ? T[(size_t)(r * m + p) * WT] : 0.0;
+            q = -nr[n + p];
+        }
 #pragma unroll
         for (int r = 0; r < NMAX; ++r) q = fma(a[r], tv[r], q);
 #pragma unroll
@@ -725,22 +763,25 @@ k_accept64f(const InstDev *__restrict__ insts, MoveArgs mv, int split, int T8) {
             if (r < n) T[(size_t)(r * m + p) * WT] = fma(-cp[r], q, tv[r]);
     }
     // rows k = part + P * i of the inverse: B[k][j] -= c'_k r_j
-    const auto rr = MDE_G(double, I.rrow) + (size_t)t * n * WT + l;
-    double *B = S.B + (size_t)w * nn;
     for (int k = part; k < n; k += split) {
         double ck = 0.0;
 #pragma unroll
         for (int r = 0; r < NMAX; ++r)
             if (r == k) ck = cp[r];
-        for (int j = g; j < n; j += NG) B[k * n + j] = fma(-ck, rr[(size_t)j * WT], B[k * n + j]);
+        for (int j = g, h = 0; j < n; j += NG, ++h) {
+            if (k == part && h < 2)
+                B[k * n + j] = fma(-ck, r0[h], b0[h]);
+            else
+                B[k * n + j] = fma(-ck, rr[(size_t)j * WT], B[k * n + j]);
+        }
     }
     // orbital row of the moved electron
     double *Phi = S.Phi + ((size_t)w * n + row) * no;
-    for (int p = part * NG + g; p < no; p += split * NG) Phi[p] = nr[p];
+    for (int p = pf; p < no; p += split * NG) Phi[p] = p == pf ? nf : nr[p];
     if (part == 0 && g == 0) {
         S.logdet[w] += log(fabs(rho));
         if (rho < 0.0) S.sgn[w] = -S.sgn[w];
-        I.Nold[w] = I.Nnew[w];
+        I.Nold[w] = nnew;
     }
 }
 

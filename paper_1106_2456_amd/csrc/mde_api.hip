@@ -749,6 +749,16 @@ static mde_status apply_plan(mde_ctx *c) {
         S.WTP = lds_row_stride(c->WT);
         S.n_tiles = (c->W + c->WT - 1) / c->WT;
         S.n_slots = (int)items.size();
+        // slots of tile t are [ts[t], ts[t + 1]); uniform counts let the
+        // finishing kernels skip that lookup
+        S.slots_per_tile = 0;
+        if (ts.size() >= 2) {
+            const int c0 = ts[1] - ts[0];
+            bool same = c0 > 0;
+            for (size_t t = 0; t + 1 < ts.size() && same; ++t)
+                same = ts[t + 1] - ts[t] == c0 && ts[t] == (int)t * c0;
+            if (same) S.slots_per_tile = c0;
+        }
         sp.ex_cap = 16;
         for (const WorkItem &it : items)
             sp.ex_cap = std::max(sp.ex_cap, item_records(sp, it.u0, it.u1, c->WT));

@@ -65,6 +65,8 @@ struct SpinDev {
     double *pc_part;         // [n_pieces][n_tiles][WT] partial sums of the pieces
     int32_t n_chunks, n_pieces, n_longs;
     int32_t n_user;          // excitations given by the caller (the dense fill follows them)
+    int32_t slots_per_tile;  // k when every tile has k items (tile t's partial-sum
+                             // slots are then [t k, t k + k)), else 0
 };
 
 // virtual-space sizes m for which the 64-walker kernel has a dense block
