@@ -1183,7 +1183,7 @@ k_precontract(const InstDev *__restrict__ insts, int spin, int ublocks) {
     if (WT == 64) {
         // One unit per wave, lanes = the tile's walkers.  The unit's terms
         // (other-spin excitation, coefficient, segment end) are uniform and
-        // read-only: scalar loads, 16 terms at a time, with the 16 ratio
+        // read-only: scalar loads, PC_BATCH terms at a time, with the PC_BATCH ratio
         // gathers in flight together.  A short segment's last term carries
         // its excitation, where the sum is written; excitations without
         // terms keep the zero the array was cleared to.
@@ -1196,34 +1196,34 @@ k_precontract(const InstDev *__restrict__ insts, int spin, int ublocks) {
         // past nk the loads read the next unit's terms or the padding:
         // valid indices, never used.  The next batch's gathers are issued
         // before this batch is summed.
-        double r[16];
+        double r[PC_BATCH];
         {
-            int oi[16];
+            int oi[PC_BATCH];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) oi[i] = oth_k[i];
+            for (int i = 0; i < PC_BATCH; ++i) oi[i] = oth_k[i];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) r[i] = Ro[(size_t)oi[i] * WT];
+            for (int i = 0; i < PC_BATCH; ++i) r[i] = Ro[(size_t)oi[i] * WT];
         }
-        for (int tb = 0; tb < nk; tb += 16) {
-            int we[16];
-            double c[16], rn[16];
+        for (int tb = 0; tb < nk; tb += PC_BATCH) {
+            int we[PC_BATCH];
+            double c[PC_BATCH], rn[PC_BATCH];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < PC_BATCH; ++i) {
                 we[i] = end_k[tb + i];
                 c[i] = cf_k[tb + i];
             }
-            if (tb + 16 < nk) {
-                int oi[16];
+            if (tb + PC_BATCH < nk) {
+                int oi[PC_BATCH];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) oi[i] = oth_k[tb + 16 + i];
+                for (int i = 0; i < PC_BATCH; ++i) oi[i] = oth_k[tb + PC_BATCH + i];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) rn[i] = Ro[(size_t)oi[i] * WT];
+                for (int i = 0; i < PC_BATCH; ++i) rn[i] = Ro[(size_t)oi[i] * WT];
             }
             // keep those loads ahead of this batch's sums (an empty asm with
             // a memory clobber emits nothing)
             __asm__ volatile("" ::: "memory");
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < PC_BATCH; ++i) {
                 if (tb + i < nk) {
                     s = fma(c[i], r[i], s);
                     if (chunk && we[i] >= 0) {
@@ -1233,7 +1233,7 @@ k_precontract(const InstDev *__restrict__ insts, int spin, int ublocks) {
                 }
             }
 #pragma unroll
-            for (int i = 0; i < 16; ++i) r[i] = rn[i];
+            for (int i = 0; i < PC_BATCH; ++i) r[i] = rn[i];
         }
         if (chunk) u = u1;
     } else

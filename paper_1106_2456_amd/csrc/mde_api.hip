@@ -641,8 +641,8 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
         SpinDev &S = h.s[s];
         S.ex = cv.take<uint4>(sp.U);
         S.ci_seg = cv.take<int32_t>(sp.U + 1);
-        S.ci_other = cv.take<int32_t>(c->n_det + 16);
-        S.ci_end = cv.take<int32_t>(c->n_det + 16);
+        S.ci_other = cv.take<int32_t>(c->n_det + PC_BATCH);
+        S.ci_end = cv.take<int32_t>(c->n_det + PC_BATCH);
         S.ci_idx = cv.take<int32_t>(c->n_det);
         S.inv_off = cv.take<int32_t>((size_t)sp.n * sp.m + 1);
         S.inv_ent = cv.take<int32_t>(sp.inv_ent.size());
@@ -660,7 +660,7 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
         S.R = cv.take<double>(Wp * sp.U);
         S.C = cv.take<double>(Wp * sp.U);
         S.partial = cv.take<double>(max_partial[s]);
-        S.coef_s = cv.take<double>(c->n_det + 16);
+        S.coef_s = cv.take<double>(c->n_det + PC_BATCH);
         S.chunks = cv.take<int32_t>(sp.chunks.size());
         S.pieces = cv.take<int4>(sp.pieces.size());
         S.longs = cv.take<int4>(sp.longs.size());
@@ -1127,13 +1127,13 @@ mde_status mde_set_ci(mde_ctx *c, int64_t n_det, const double *coef, const int32
         }
         if (cur < sp.U) { starts.push_back(cur); ends.push_back(sp.U); }
         // the last term of every short segment names its excitation; the
-        // term arrays carry 16 entries of padding (read, never used)
-        sp.ci_end.assign(n_det + 16, -1);
+        // term arrays carry PC_BATCH entries of padding (read, never used)
+        sp.ci_end.assign(n_det + PC_BATCH, -1);
         for (int u = 0; u < sp.U; ++u) {
             const int len = sp.ci_seg[u + 1] - sp.ci_seg[u];
             if (len > 0 && len <= PIECE) sp.ci_end[sp.ci_seg[u + 1] - 1] = u;
         }
-        sp.ci_other.resize(n_det + 16, 0);
+        sp.ci_other.resize(n_det + PC_BATCH, 0);
         // chunks as (start, end) pairs flattened: chunks[2c], chunks[2c+1]
         sp.chunks.clear();
         for (size_t i = 0; i < starts.size(); ++i) {
@@ -1198,11 +1198,11 @@ mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
         MDE_HIP(c, hipMemcpy((void *)S.ex, sp.ex.data(), sizeof(uint4) * sp.U, hipMemcpyHostToDevice));
         MDE_HIP(c, hipMemcpy((void *)S.ci_seg, sp.ci_seg.data(), sizeof(int) * (sp.U + 1),
                              hipMemcpyHostToDevice));
-        MDE_HIP(c, hipMemcpy((void *)S.ci_other, sp.ci_other.data(), sizeof(int) * (c->n_det + 16),
+        MDE_HIP(c, hipMemcpy((void *)S.ci_other, sp.ci_other.data(), sizeof(int) * (c->n_det + PC_BATCH),
                              hipMemcpyHostToDevice));
-        MDE_HIP(c, hipMemcpy((void *)S.ci_end, sp.ci_end.data(), sizeof(int) * (c->n_det + 16),
+        MDE_HIP(c, hipMemcpy((void *)S.ci_end, sp.ci_end.data(), sizeof(int) * (c->n_det + PC_BATCH),
                              hipMemcpyHostToDevice));
-        MDE_HIP(c, hipMemset(S.coef_s + c->n_det, 0, sizeof(double) * 16));
+        MDE_HIP(c, hipMemset(S.coef_s + c->n_det, 0, sizeof(double) * PC_BATCH));
         MDE_HIP(c, hipMemcpy((void *)S.ci_idx, sp.ci_idx.data(), sizeof(int) * c->n_det,
                              hipMemcpyHostToDevice));
         MDE_HIP(c, hipMemcpy((void *)S.chunks, sp.chunks.data(), sizeof(int) * sp.chunks.size(),

@@ -38,8 +38,8 @@ struct SpinDev {
     int32_t dense_k;
     const uint4 *ex;          // [U] packed: bytes 0..7 holes, 8..15 particles - n
     const int32_t *ci_seg;    // [U+1] CI terms of this spin's excitation u
-    const int32_t *ci_other;  // [n_det + 16] other spin's excitation, per term (0 past the end)
-    const int32_t *ci_end;    // [n_det + 16] u when the term is the last of u's short CI
+    const int32_t *ci_other;  // [n_det + PC_BATCH] other spin's excitation, per term (0 past the end)
+    const int32_t *ci_end;    // [n_det + PC_BATCH] u when the term is the last of u's short CI
                               // segment, else -1
     const int32_t *ci_idx;    // [n_det] original determinant index, per term
     const int32_t *inv_off;   // [n*m+1] adjoint inverted index by entry
@@ -58,7 +58,7 @@ struct SpinDev {
     double *R;       // [n_tiles][U][WT] excited ratios at current positions
     double *C;       // [n_tiles][U][WT] CI weights: sum over terms of c_I R_other
     double *partial; // [n_slots][WT][NSUM]
-    double *coef_s;  // [n_det + 16] c_I in this spin's CI-term order
+    double *coef_s;  // [n_det + PC_BATCH] c_I in this spin's CI-term order
     const int32_t *chunks;   // [2*n_chunks] (first, end) excitation ranges of the precontraction
     const int4 *pieces;      // [n_pieces] (u, k0, k1, -) pieces of long CI segments
     const int4 *longs;       // [n_longs] (u, first piece, end piece, -)
@@ -155,6 +155,9 @@ constexpr int ITEM_MAX = 1024;
 // threads of a 64-walker determinant block: eight waves, so each wave may
 // hold a hole set's table rows in registers (up to 256 VGPRs)
 constexpr int DET64_THREADS = 512;
+// CI terms the 64-walker precontraction takes per step (the term arrays
+// carry this many entries of padding)
+constexpr int PC_BATCH = 16;
 // LDS row stride of a walker tile's tables: 64-walker rows are read whole
 // (one 512-byte row per wave) and need no padding; smaller tiles pad by one
 // element against bank conflicts between lanes reading different rows
