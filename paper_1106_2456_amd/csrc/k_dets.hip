@@ -793,8 +793,11 @@ __device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, con
     __syncthreads();
     double acc[NSUM] = {0, 0, 0, 0, 0, 0};
     {
-        // wave `wave` takes its cost-balanced range of the item, order by order
-        const int ws = __builtin_amdgcn_readfirstlane(wave);
+        // each wave takes one cost-balanced range of the item, order by
+        // order, in reverse: the ranges run from the dense block (cheapest
+        // per unit of cost) to the sparse high orders, and a SIMD issues its
+        // older waves first, so the last ranges go to the first waves
+        const int ws = __builtin_amdgcn_readfirstlane(nw - 1 - wave);
         const int j0 = bounds[it.wb + 2 * ws], j1 = bounds[it.wb + 2 * ws + 1];
         for (int k = 1; k <= S.max_order; ++k) {
             const int a = max(j0, S.order_start[k]), b = min(j1, S.order_start[k + 1]);
