@@ -652,17 +652,36 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
     const int w0 = it.tile * WT;
     const auto orb = MDE_G(double, mv.new_orb);
     __syncthreads();   // all waves done: W final, Tab and c intact
+    // (the sums below read all their terms before adding them, in the same
+    // order as a plain loop: the reads overlap, the result is unchanged)
+    constexpr int NWMAX = DET64_THREADS / 64;
     for (int idx = tid; idx < m * 64; idx += nthr) {
         const int q = idx >> 6, l = idx & 63;
+        double wv[NWMAX];
+#pragma unroll
+        for (int v = 0; v < NWMAX; ++v) wv[v] = v < nw ? Wall[((size_t)v * m + q) * 64 + l] : 0.0;
         double w = 0.0;
-        for (int v = 0; v < nw; ++v) w += Wall[((size_t)v * m + q) * 64 + l];
+#pragma unroll
+        for (int v = 0; v < NWMAX; ++v)
+            if (v < nw) w += wv[v];
         Wall[idx] = w;     // this thread alone reads and writes entry (q, l)
     }
     __syncthreads();
     for (int idx = tid; idx < n * 64; idx += nthr) {
         const int r = idx >> 6, l = idx & 63;
         double v = 0.0;
-        for (int q = 0; q < m; ++q) v = fma(Wall[q * 64 + l], tabs[(r * m + q) * WTP + l], v);
+        int q = 0;
+        for (; q + 4 <= m; q += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = Wall[(q + u) * 64 + l];
+                b[u] = tabs[(r * m + q + u) * WTP + l];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v = fma(a[u], b[u], v);
+        }
+        for (; q < m; ++q) v = fma(Wall[q * 64 + l], tabs[(r * m + q) * WTP + l], v);
         Vs[idx] = v;
     }
     __syncthreads();
@@ -708,9 +727,15 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
     const auto pout = MDE_GW(double, S.partial);
     for (int idx = tid; idx < 64 * NSUM; idx += nthr) {
         const int l = idx / NSUM, q = idx - l * NSUM;
+        double rv[NWMAX];
+#pragma unroll
+        for (int v = 0; v < NWMAX; ++v) rv[v] = v < nw ? red[((size_t)v * NSUM + q) * 64 + l] : 0.0;
+        const double r2 = q >= 1 ? red2[(q - 1) * 64 + l] : 0.0;
         double sum = 0.0;
-        for (int v = 0; v < nw; ++v) sum += red[((size_t)v * NSUM + q) * 64 + l];
-        if (q >= 1) sum += red2[(q - 1) * 64 + l];
+#pragma unroll
+        for (int v = 0; v < NWMAX; ++v)
+            if (v < nw) sum += rv[v];
+        if (q >= 1) sum += r2;
         pout[((size_t)it.slot * 64 + l) * NSUM + q] = sum;
     }
     __syncthreads();
