@@ -159,6 +159,11 @@ __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
 
 __device__ __forceinline__ int byte_of(uint32_t w, int i) { return (int)((w >> (8 * i)) & 0xffu); }
 
+// CI weights C_u are read with non-temporal loads in the proposal: a launch
+// reads each weight once, and streaming them through L2 at the normal
+// priority evicts the tables, inverses and partial sums that the kernels
+// around the proposal hand to each other through L2.
+
 template <int K, typename TT, int MODE>
 __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, int j1,
                                            const uint32_t *exw, int u0,
@@ -259,7 +264,7 @@ __device__ __forceinline__ void det_runs64(const SpinDev &S, int tile, int j0, i
             const int jj = min(jb + i, j1 - 1);
             h[i] = exw[4 * (jj - u0)];          // word x: holes 0..3
             pp[i] = exw[4 * (jj - u0) + 2];     // word z: particles 0..3
-            cv[i] = MODE == DM_PROPOSE ? Cg[(size_t)jj * 64] : 0.0;
+            cv[i] = MODE == DM_PROPOSE ? __builtin_nontemporal_load(&Cg[(size_t)jj * 64]) : 0.0;
         }
         // keep the compiler from moving these loads next to their use one
         // group later (an empty asm with a memory clobber emits nothing)
@@ -315,7 +320,7 @@ __device__ __forceinline__ void det_direct64(const SpinDev &S, int tile, int j0,
             const int jj = min(jb + i, j1 - 1);
             h[i] = exw[4 * (jj - u0)];          // word x: holes 0..3
             pp[i] = exw[4 * (jj - u0) + 2];     // word z: particles 0..3
-            cv[i] = MODE == DM_PROPOSE ? Cg[(size_t)jj * 64] : 0.0;
+            cv[i] = MODE == DM_PROPOSE ? __builtin_nontemporal_load(&Cg[(size_t)jj * 64]) : 0.0;
         }
         __asm__ volatile("" ::: "memory");
     };
@@ -382,7 +387,7 @@ __device__ void det_generic64(const SpinDev &S, int tile, int k, int j0, int j1,
         ex.y = __builtin_amdgcn_readfirstlane(ex.y);
         ex.z = __builtin_amdgcn_readfirstlane(ex.z);
         ex.w = __builtin_amdgcn_readfirstlane(ex.w);
-        const double Cu = MODE == DM_PROPOSE ? Cg[(size_t)j * 64] : 0.0;
+        const double Cu = MODE == DM_PROPOSE ? __builtin_nontemporal_load(&Cg[(size_t)j * 64]) : 0.0;
         const double R = det_one_generic<TT, MODE, true>(k, ex, tabs, nullptr, cs, S.m,
                                                          lds_row_stride(64), wl, Cu, acc, Wl);
         if (MODE == DM_VALUES) Rg[(size_t)j * 64] = R;
@@ -466,7 +471,7 @@ __device__ __forceinline__ void dense2_unit(const double (&a)[M], const double (
                 continue;
             }
             const double C = cb[x % PD];
-            cb[x % PD] = Cg[(size_t)min(base + x + PD, j1 - 1) * 64];
+            cb[x % PD] = __builtin_nontemporal_load(&Cg[(size_t)min(base + x + PD, j1 - 1) * 64]);
             __asm__ volatile("" ::: "memory");
             S1 = fma(C, b[q], S1);
             S2 = fma(C, a[q], S2);
@@ -514,7 +519,7 @@ __device__ __forceinline__ void det_dense(const SpinDev &S, int k, int tile, int
         double cb[PD];
         if (MODE == DM_PROPOSE) {
 #pragma unroll
-            for (int i = 0; i < PD; ++i) cb[i] = Cg[(size_t)min(j0 + i, j1 - 1) * 64];
+            for (int i = 0; i < PD; ++i) cb[i] = __builtin_nontemporal_load(&Cg[(size_t)min(j0 + i, j1 - 1) * 64]);
         }
         for (int base = j0; base < j1; base += M) {
             const int h = (base - a0) / M;
@@ -531,7 +536,7 @@ __device__ __forceinline__ void det_dense(const SpinDev &S, int k, int tile, int
 #pragma unroll
             for (int q = 0; q < M; ++q) {
                 const double C = cb[q % PD];
-                cb[q % PD] = Cg[(size_t)min(base + q + PD, j1 - 1) * 64];
+                cb[q % PD] = __builtin_nontemporal_load(&Cg[(size_t)min(base + q + PD, j1 - 1) * 64]);
                 __asm__ volatile("" ::: "memory");
                 s0 = fma(C, a[q], s0);
                 Wt[q] = fma(C, ch, Wt[q]);
@@ -544,7 +549,7 @@ __device__ __forceinline__ void det_dense(const SpinDev &S, int k, int tile, int
         double cb[PD];
         if (MODE == DM_PROPOSE) {
 #pragma unroll
-            for (int i = 0; i < PD; ++i) cb[i] = Cg[(size_t)min(j0 + i, j1 - 1) * 64];
+            for (int i = 0; i < PD; ++i) cb[i] = __builtin_nontemporal_load(&Cg[(size_t)min(j0 + i, j1 - 1) * 64]);
         }
         // hole pair and unit of the first excitation of the range
         int hp = (j0 - a0) / NP, h0 = 0;
