@@ -1219,7 +1219,9 @@ k_precontract(const InstDev *__restrict__ insts, int spin, int ublocks) {
         // read-only: scalar loads, PC_BATCH terms at a time, with the PC_BATCH ratio
         // gathers in flight together.  A short segment's last term carries
         // its excitation, where the sum is written; excitations without
-        // terms keep the zero the array was cleared to.
+        // terms keep the zero the array was cleared to.  The weights are
+        // stored non-temporally: they are read back only by later launches,
+        // and the other spin's ratios the gathers reuse stay in L2.
         const int kb = __builtin_amdgcn_readfirstlane(k0);
         const int nk = __builtin_amdgcn_readfirstlane(k1) - kb;
         const auto oth_k = MDE_K(int32_t, S.ci_other) + kb;
@@ -1260,7 +1262,7 @@ k_precontract(const InstDev *__restrict__ insts, int spin, int ublocks) {
                 if (tb + i < nk) {
                     s = fma(c[i], r[i], s);
                     if (chunk && we[i] >= 0) {
-                        Cw[(size_t)we[i] * WT] = s;
+                        __builtin_nontemporal_store(s, &Cw[(size_t)we[i] * WT]);
                         s = 0.0;
                     }
                 }
