@@ -140,6 +140,171 @@ hipError_t launch_lu_inverse(hipStream_t st, const InstDev *d_inst, const InstDe
 }
 
 // ---------------------------------------------------------------------------
+// Refresh of a spin with at most 8 electrons, a thread per walker: the same
+// LU with partial pivoting (largest |A[i][k]|, first on ties), inverse by
+// forward and back substitution and table T_V = A^-1 Phi_V as the two
+// kernels around this one, in the same operation order, with the walker's
+// matrix in registers.
+// ---------------------------------------------------------------------------
+
+template <int N>
+__global__ void __launch_bounds__(64)
+k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__restrict__ orb_in,
+                int32_t *status) {
+    const InstDev &I = insts[0];
+    const SpinDev &S = I.s[spin];
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= I.W) return;
+    const int no = S.no, m = S.m;
+    double *Phw = S.Phi + (size_t)w * N * no;
+    if (orb_in) {
+        for (int i = 0; i < N; ++i)
+            for (int p = 0; p < no; ++p) {
+                const double v = orb_in[((size_t)(w * N + i) * 5) * no + p];
+                Phw[i * no + p] = v;
+                if (I.prec == 2 && p >= N) S.PhiV32[((size_t)w * N + i) * m + (p - N)] = (float)v;
+            }
+    } else if (I.prec == 2) {
+        for (int i = 0; i < N; ++i)
+            for (int p = 0; p < m; ++p) S.PhiV32[((size_t)w * N + i) * m + p] = (float)Phw[i * no + N + p];
+    }
+    double A[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            A[i][j] = orb_in ? orb_in[((size_t)(w * N + i) * 5) * no + j] : Phw[i * no + j];
+    double sg = 1.0, la = 0.0;
+    bool sing = false;
+    int pv[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        pv[k] = k;
+        if (sing) continue;
+        int p = k;
+        double best = fabs(A[k][k]);
+#pragma unroll
+        for (int i = k + 1; i < N; ++i)
+            if (fabs(A[i][k]) > best) {
+                best = fabs(A[i][k]);
+                p = i;
+            }
+        if (!(best > 0.0)) {
+            sing = true;
+            continue;
+        }
+        if (p != k) {
+#pragma unroll
+            for (int i = k + 1; i < N; ++i)
+                if (i == p) {
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {
+                        const double t = A[k][j];
+                        A[k][j] = A[i][j];
+                        A[i][j] = t;
+                    }
+                }
+            sg = -sg;
+        }
+        pv[k] = p;
+        const double piv = A[k][k];
+        if (piv < 0.0) sg = -sg;
+        la += log(fabs(piv));
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const double f = A[i][k] / piv;
+            A[i][k] = f;
+#pragma unroll
+            for (int j = k + 1; j < N; ++j) A[i][j] = fma(-f, A[k][j], A[i][j]);
+        }
+    }
+    double *Bw = S.B + (size_t)w * N * N;
+    double Binv[N][N];
+    if (sing) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) Binv[i][j] = 0.0;
+        S.logdet[w] = -INFINITY;
+        S.sgn[w] = 0.0;
+        I.st[w] |= 1;
+        if (status) status[w] |= 1;
+    } else {
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            double x[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) x[i] = i == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+#pragma unroll
+                for (int i = k + 1; i < N; ++i)
+                    if (pv[k] == i) {
+                        const double t = x[k];
+                        x[k] = x[i];
+                        x[i] = t;
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double s = x[i];
+#pragma unroll
+                for (int kk = 0; kk < i; ++kk) s = fma(-A[i][kk], x[kk], s);
+                x[i] = s;
+            }
+#pragma unroll
+            for (int i = N - 1; i >= 0; --i) {
+                double s = x[i];
+#pragma unroll
+                for (int kk = i + 1; kk < N; ++kk) s = fma(-A[i][kk], x[kk], s);
+                x[i] = s / A[i][i];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) Binv[i][c] = x[i];
+        }
+        S.logdet[w] = la;
+        S.sgn[w] = sg;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) Bw[i * N + j] = Binv[i][j];
+    // T_V = A^-1 Phi_V, walker-tiled
+    const int WT = S.WT;
+    const size_t tb = (size_t)(w / WT) * N * m * WT + (w % WT);
+    for (int p = 0; p < m; ++p) {
+        double ph[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) ph[k] = Phw[k * no + N + p];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) s = fma(Binv[r][k], ph[k], s);
+            const size_t o = tb + ((size_t)r * m + p) * WT;
+            if (I.prec == 0) S.T[o] = s;
+            else S.T32[o] = (float)s;
+        }
+    }
+}
+
+hipError_t launch_refresh_small(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
+                                const double *orb_in, int32_t *status) {
+    const dim3 grid((h.W + 63) / 64);
+#define MDE_RS(X)                                                                          \
+    case X:                                                                                \
+        hipLaunchKernelGGL(k_refresh_small<X>, grid, dim3(64), 0, st, d_inst, spin, orb_in, \
+                           status);                                                        \
+        break;
+    switch (h.s[spin].n) {
+        MDE_RS(1) MDE_RS(2) MDE_RS(3) MDE_RS(4) MDE_RS(5) MDE_RS(6) MDE_RS(7) MDE_RS(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef MDE_RS
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // table GEMM in FP64: T_V[w] = A^-1[w] Phi_V[w], one block per walker,
 // 64-column chunks of Phi_V staged in LDS.  In MIXED mode the FP32 table is
 // the rounded FP64 product at a refresh.

@@ -853,8 +853,12 @@ static mde_status full_eval(mde_ctx *c, const double *orb_up, const double *orb_
     const double *orb[2] = {orb_up, orb_dn};
     MDE_HIP(c, launch_coef_gather(c->stream, c->d_inst, c->h, c->h.coef));
     for (int s = 0; s < 2; ++s) {
-        MDE_HIP(c, launch_lu_inverse(c->stream, c->d_inst, c->h, s, orb[s], status));
-        MDE_HIP(c, launch_table_gemm(c->stream, c->d_inst, c->h, s));
+        if (c->sp[s].n <= 8) {
+            MDE_HIP(c, launch_refresh_small(c->stream, c->d_inst, c->h, s, orb[s], status));
+        } else {
+            MDE_HIP(c, launch_lu_inverse(c->stream, c->d_inst, c->h, s, orb[s], status));
+            MDE_HIP(c, launch_table_gemm(c->stream, c->d_inst, c->h, s));
+        }
     }
     c->R_valid[0] = c->R_valid[1] = false;
     c->C_valid[0] = c->C_valid[1] = false;

@@ -196,6 +196,10 @@ __device__ __forceinline__ bool tile_of_block(int split, int T8, int n_inst, int
 
 hipError_t launch_lu_inverse(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
                              int spin, const double *orb_in, int32_t *status);
+// both of the above in one launch, a thread per walker (n <= 8); returns
+// hipErrorInvalidValue for larger n
+hipError_t launch_refresh_small(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
+                                int spin, const double *orb_in, int32_t *status);
 hipError_t launch_table_gemm(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
                              int spin);
 hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
