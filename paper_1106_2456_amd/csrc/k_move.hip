@@ -140,12 +140,15 @@ hipError_t launch_lu_inverse(hipStream_t st, const InstDev *d_inst, const InstDe
 }
 
 // ---------------------------------------------------------------------------
-// Refresh of a spin with at most 8 electrons, a thread per walker: the same
-// LU with partial pivoting (largest |A[i][k]|, first on ties), inverse by
-// forward and back substitution and table T_V = A^-1 Phi_V as the two
-// kernels around this one, in the same operation order, with the walker's
-// matrix in registers.
+// Refresh of a spin with at most 8 electrons, RPW threads per walker: each
+// factors the walker's matrix in registers (LU with partial pivoting, the
+// largest |A[i][k]| and the first on ties), forms the inverse by forward and
+// back substitution with the pivots' reciprocals, and writes its share of
+// the rows of the inverse and of the table T_V = A^-1 Phi_V.
+// log|det| = log of the pivots' mantissa product + their exponent sum x ln 2.
 // ---------------------------------------------------------------------------
+
+constexpr int RPW = 4;
 
 template <int N>
 __global__ void __launch_bounds__(64)
@@ -153,33 +156,58 @@ k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__res
                 int32_t *status) {
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[spin];
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = tid / RPW, g = tid - w * RPW;
     if (w >= I.W) return;
-    const int no = S.no, m = S.m;
-    double *Phw = S.Phi + (size_t)w * N * no;
+    // fields read once: the stores below could alias them otherwise
+    const int no = S.no, m = S.m, prec = I.prec, WT = S.WT;
+    double *const Tg = S.T;
+    float *const T32 = S.T32;
+    float *const PV32 = S.PhiV32;
+    double *const Phw = S.Phi + (size_t)w * N * no;
+    double *const Bw = S.B + (size_t)w * N * N;
+    const auto orow = [&](int i) { return orb_in + ((size_t)(w * N + i) * 5) * no; };
     if (orb_in) {
-        for (int i = 0; i < N; ++i)
-            for (int p = 0; p < no; ++p) {
-                const double v = orb_in[((size_t)(w * N + i) * 5) * no + p];
-                Phw[i * no + p] = v;
-                if (I.prec == 2 && p >= N) S.PhiV32[((size_t)w * N + i) * m + (p - N)] = (float)v;
+        // the kept copy of the walker's orbital rows (rows i = g, g + RPW, ..)
+        for (int i = g; i < N; i += RPW)
+            for (int p0 = 0; p0 < no; p0 += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = p0 + u < no ? orow(i)[p0 + u] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int p = p0 + u;
+                    if (p >= no) break;
+                    Phw[i * no + p] = v[u];
+                    if (prec == 2 && p >= N) PV32[((size_t)w * N + i) * m + (p - N)] = (float)v[u];
+                }
             }
-    } else if (I.prec == 2) {
-        for (int i = 0; i < N; ++i)
-            for (int p = 0; p < m; ++p) S.PhiV32[((size_t)w * N + i) * m + p] = (float)Phw[i * no + N + p];
+    } else if (prec == 2) {
+        for (int i = g; i < N; i += RPW)
+            for (int p = 0; p < m; ++p) PV32[((size_t)w * N + i) * m + p] = (float)Phw[i * no + N + p];
     }
     double A[N][N];
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int j = 0; j < N; ++j)
-            A[i][j] = orb_in ? orb_in[((size_t)(w * N + i) * 5) * no + j] : Phw[i * no + j];
-    double sg = 1.0, la = 0.0;
+        for (int j = 0; j < N; ++j) A[i][j] = orb_in ? orow(i)[j] : Phw[i * no + j];
+    // the table rows of this thread: r = g, g + RPW; columns PB at a time,
+    // the next chunk issued before the current one is stored (the first
+    // before the factorisation)
+    constexpr int PB = 8;
+    auto phi_v = [&](int i, int p) { return orb_in ? orow(i)[N + p] : Phw[i * no + N + p]; };
+    double ph[PB][N];
+#pragma unroll
+    for (int u = 0; u < PB; ++u)
+#pragma unroll
+        for (int k = 0; k < N; ++k) ph[u][k] = u < m ? phi_v(k, u) : 0.0;
+    double sg = 1.0, mant = 1.0, rp[N];
+    int ex = 0, pv[N];
     bool sing = false;
-    int pv[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         pv[k] = k;
+        rp[k] = 0.0;
         if (sing) continue;
         int p = k;
         double best = fabs(A[k][k]);
@@ -209,88 +237,100 @@ k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__res
         pv[k] = p;
         const double piv = A[k][k];
         if (piv < 0.0) sg = -sg;
-        la += log(fabs(piv));
+        int e;
+        mant *= frexp(fabs(piv), &e);
+        ex += e;
+        rp[k] = 1.0 / piv;
 #pragma unroll
         for (int i = k + 1; i < N; ++i) {
-            const double f = A[i][k] / piv;
+            const double f = A[i][k] * rp[k];
             A[i][k] = f;
 #pragma unroll
             for (int j = k + 1; j < N; ++j) A[i][j] = fma(-f, A[k][j], A[i][j]);
         }
     }
-    double *Bw = S.B + (size_t)w * N * N;
     double Binv[N][N];
-    if (sing) {
 #pragma unroll
-        for (int i = 0; i < N; ++i)
+    for (int c = 0; c < N; ++c) {
+        double x[N];
 #pragma unroll
-            for (int j = 0; j < N; ++j) Binv[i][j] = 0.0;
-        S.logdet[w] = -INFINITY;
-        S.sgn[w] = 0.0;
-        I.st[w] |= 1;
-        if (status) status[w] |= 1;
-    } else {
+        for (int i = 0; i < N; ++i) x[i] = i == c ? 1.0 : 0.0;
 #pragma unroll
-        for (int c = 0; c < N; ++c) {
-            double x[N];
+        for (int k = 0; k < N; ++k)
 #pragma unroll
-            for (int i = 0; i < N; ++i) x[i] = i == c ? 1.0 : 0.0;
+            for (int i = k + 1; i < N; ++i)
+                if (pv[k] == i) {
+                    const double t = x[k];
+                    x[k] = x[i];
+                    x[i] = t;
+                }
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
+        for (int i = 0; i < N; ++i) {
+            double s = x[i];
 #pragma unroll
-                for (int i = k + 1; i < N; ++i)
-                    if (pv[k] == i) {
-                        const double t = x[k];
-                        x[k] = x[i];
-                        x[i] = t;
-                    }
-            }
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                double s = x[i];
-#pragma unroll
-                for (int kk = 0; kk < i; ++kk) s = fma(-A[i][kk], x[kk], s);
-                x[i] = s;
-            }
-#pragma unroll
-            for (int i = N - 1; i >= 0; --i) {
-                double s = x[i];
-#pragma unroll
-                for (int kk = i + 1; kk < N; ++kk) s = fma(-A[i][kk], x[kk], s);
-                x[i] = s / A[i][i];
-            }
-#pragma unroll
-            for (int i = 0; i < N; ++i) Binv[i][c] = x[i];
+            for (int kk = 0; kk < i; ++kk) s = fma(-A[i][kk], x[kk], s);
+            x[i] = s;
         }
-        S.logdet[w] = la;
-        S.sgn[w] = sg;
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+            double s = x[i];
+#pragma unroll
+            for (int kk = i + 1; kk < N; ++kk) s = fma(-A[i][kk], x[kk], s);
+            x[i] = s * rp[i];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) Binv[i][c] = sing ? 0.0 : x[i];
+    }
+    if (g == 0) {
+        if (sing) {
+            S.logdet[w] = -INFINITY;
+            S.sgn[w] = 0.0;
+            I.st[w] |= 1;
+            if (status) status[w] |= 1;
+        } else {
+            S.logdet[w] = log(mant) + ex * 0.69314718055994530942;
+            S.sgn[w] = sg;
+        }
     }
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+    for (int r = 0; r < N; ++r)
+        if (r % RPW == g)
 #pragma unroll
-        for (int j = 0; j < N; ++j) Bw[i * N + j] = Binv[i][j];
+            for (int j = 0; j < N; ++j) Bw[r * N + j] = Binv[r][j];
     // T_V = A^-1 Phi_V, walker-tiled
-    const int WT = S.WT;
     const size_t tb = (size_t)(w / WT) * N * m * WT + (w % WT);
-    for (int p = 0; p < m; ++p) {
-        double ph[N];
+    for (int p0 = 0; p0 < m; p0 += PB) {
+        double pn[PB][N];
+        if (p0 + PB < m) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) ph[k] = Phw[k * no + N + p];
+            for (int u = 0; u < PB; ++u)
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < N; ++k) s = fma(Binv[r][k], ph[k], s);
-            const size_t o = tb + ((size_t)r * m + p) * WT;
-            if (I.prec == 0) S.T[o] = s;
-            else S.T32[o] = (float)s;
+                for (int k = 0; k < N; ++k) pn[u][k] = p0 + PB + u < m ? phi_v(k, p0 + PB + u) : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            if (p0 + u >= m) break;
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                if (r % RPW != g) continue;
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) s = fma(Binv[r][k], ph[u][k], s);
+                const size_t o = tb + ((size_t)r * m + p0 + u) * WT;
+                if (prec == 0) Tg[o] = s;
+                else T32[o] = (float)s;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u)
+#pragma unroll
+            for (int k = 0; k < N; ++k) ph[u][k] = pn[u][k];
     }
 }
 
 hipError_t launch_refresh_small(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
                                 const double *orb_in, int32_t *status) {
-    const dim3 grid((h.W + 63) / 64);
+    const dim3 grid((unsigned)(((size_t)h.W * RPW + 63) / 64));
 #define MDE_RS(X)                                                                          \
     case X:                                                                                \
         hipLaunchKernelGGL(k_refresh_small<X>, grid, dim3(64), 0, st, d_inst, spin, orb_in, \
