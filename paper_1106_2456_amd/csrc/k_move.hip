@@ -140,67 +140,65 @@ hipError_t launch_lu_inverse(hipStream_t st, const InstDev *d_inst, const InstDe
 }
 
 // ---------------------------------------------------------------------------
-// Refresh of a spin with at most 8 electrons, RPW threads per walker: each
-// factors the walker's matrix in registers (LU with partial pivoting, the
-// largest |A[i][k]| and the first on ties), forms the inverse by forward and
-// back substitution with the pivots' reciprocals, and writes its share of
-// the rows of the inverse and of the table T_V = A^-1 Phi_V.
-// log|det| = log of the pivots' mantissa product + their exponent sum x ln 2.
+// Refresh of a spin with at most 8 electrons, eight lanes per walker: lane g
+// holds row g of the walker's matrix.  LU with partial pivoting (the largest
+// |A[i][k]|, the first on ties) with the pivot found and the rows swapped
+// across the lane group; lane c then solves for column c of the inverse
+// (forward and back substitution with the pivots' reciprocals); the columns
+// are transposed through LDS and lane r writes row r of the inverse and of
+// the table T_V = A^-1 Phi_V.  log|det| = log of the pivots' mantissa
+// product + their exponent sum x ln 2.
 // ---------------------------------------------------------------------------
-
-constexpr int RPW = 4;
 
 template <int N>
 __global__ void __launch_bounds__(64)
 k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__restrict__ orb_in,
                 int32_t *status) {
+    constexpr int G = 8;                     // lanes per walker
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[spin];
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int w = tid / RPW, g = tid - w * RPW;
-    if (w >= I.W) return;
+    const int w = tid / G, g = tid % G, wl = threadIdx.x / G;
     // fields read once: the stores below could alias them otherwise
-    const int no = S.no, m = S.m, prec = I.prec, WT = S.WT;
+    const int no = S.no, m = S.m, prec = I.prec, WT = S.WT, W = I.W;
     double *const Tg = S.T;
     float *const T32 = S.T32;
     float *const PV32 = S.PhiV32;
-    double *const Phw = S.Phi + (size_t)w * N * no;
-    double *const Bw = S.B + (size_t)w * N * N;
-    const auto orow = [&](int i) { return orb_in + ((size_t)(w * N + i) * 5) * no; };
-    if (orb_in) {
-        // the kept copy of the walker's orbital rows (rows i = g, g + RPW, ..)
-        for (int i = g; i < N; i += RPW)
-            for (int p0 = 0; p0 < no; p0 += 8) {
-                double v[8];
+    __shared__ double tr[64 / G][N][N];
+    const bool live = w < W;                 // uniform over a lane group
+    const bool row = live && g < N;
+    double *const Phw = S.Phi + (size_t)(live ? w : 0) * N * no;
+    double *const Bw = S.B + (size_t)(live ? w : 0) * N * N;
+    const auto orow = [&](int i) { return orb_in + ((size_t)((live ? w : 0) * N + i) * 5) * no; };
+    if (row && orb_in) {
+        // the kept copy of the walker's orbital rows
+        for (int p0 = 0; p0 < no; p0 += 8) {
+            double v[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = p0 + u < no ? orow(i)[p0 + u] : 0.0;
+            for (int u = 0; u < 8; ++u) v[u] = p0 + u < no ? orow(g)[p0 + u] : 0.0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int p = p0 + u;
-                    if (p >= no) break;
-                    Phw[i * no + p] = v[u];
-                    if (prec == 2 && p >= N) PV32[((size_t)w * N + i) * m + (p - N)] = (float)v[u];
-                }
+            for (int u = 0; u < 8; ++u) {
+                const int p = p0 + u;
+                if (p >= no) break;
+                Phw[g * no + p] = v[u];
+                if (prec == 2 && p >= N) PV32[((size_t)w * N + g) * m + (p - N)] = (float)v[u];
             }
-    } else if (prec == 2) {
-        for (int i = g; i < N; i += RPW)
-            for (int p = 0; p < m; ++p) PV32[((size_t)w * N + i) * m + p] = (float)Phw[i * no + N + p];
+        }
+    } else if (row && prec == 2) {
+        for (int p = 0; p < m; ++p) PV32[((size_t)w * N + g) * m + p] = (float)Phw[g * no + N + p];
     }
-    double A[N][N];
+    double a[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int j = 0; j < N; ++j) A[i][j] = orb_in ? orow(i)[j] : Phw[i * no + j];
-    // the table rows of this thread: r = g, g + RPW; columns PB at a time,
-    // the next chunk issued before the current one is stored (the first
-    // before the factorisation)
+    for (int j = 0; j < N; ++j) a[j] = row ? (orb_in ? orow(g)[j] : Phw[g * no + j]) : 0.0;
+    // the table's columns are read PB at a time, the next chunk issued before
+    // the current one is stored (the first before the factorisation)
     constexpr int PB = 8;
     auto phi_v = [&](int i, int p) { return orb_in ? orow(i)[N + p] : Phw[i * no + N + p]; };
     double ph[PB][N];
 #pragma unroll
     for (int u = 0; u < PB; ++u)
 #pragma unroll
-        for (int k = 0; k < N; ++k) ph[u][k] = u < m ? phi_v(k, u) : 0.0;
+        for (int k = 0; k < N; ++k) ph[u][k] = (row && u < m) ? phi_v(k, u) : 0.0;
     double sg = 1.0, mant = 1.0, rp[N];
     int ex = 0, pv[N];
     bool sing = false;
@@ -208,79 +206,85 @@ k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__res
     for (int k = 0; k < N; ++k) {
         pv[k] = k;
         rp[k] = 0.0;
-        if (sing) continue;
-        int p = k;
-        double best = fabs(A[k][k]);
+        // pivot: the largest |A[i][k]| over rows i >= k, the first on ties
+        double v = (row && g >= k) ? fabs(a[k]) : -1.0;
+        int idx = g;
 #pragma unroll
-        for (int i = k + 1; i < N; ++i)
-            if (fabs(A[i][k]) > best) {
-                best = fabs(A[i][k]);
-                p = i;
+        for (int off = G / 2; off >= 1; off >>= 1) {
+            const double ov = __shfl_xor(v, off, G);
+            const int oi = __shfl_xor(idx, off, G);
+            if (ov > v || (ov == v && oi < idx)) {
+                v = ov;
+                idx = oi;
             }
-        if (!(best > 0.0)) {
+        }
+        if (sing) continue;
+        if (!(v > 0.0)) {
             sing = true;
             continue;
         }
+        const int p = idx;
+        pv[k] = p;
         if (p != k) {
+            const int src = g == k ? p : (g == p ? k : g);
 #pragma unroll
-            for (int i = k + 1; i < N; ++i)
-                if (i == p) {
-#pragma unroll
-                    for (int j = 0; j < N; ++j) {
-                        const double t = A[k][j];
-                        A[k][j] = A[i][j];
-                        A[i][j] = t;
-                    }
-                }
+            for (int j = 0; j < N; ++j) a[j] = __shfl(a[j], src, G);
             sg = -sg;
         }
-        pv[k] = p;
-        const double piv = A[k][k];
+        const double piv = __shfl(a[k], k, G);
         if (piv < 0.0) sg = -sg;
         int e;
         mant *= frexp(fabs(piv), &e);
         ex += e;
         rp[k] = 1.0 / piv;
+        double rk[N];
 #pragma unroll
-        for (int i = k + 1; i < N; ++i) {
-            const double f = A[i][k] * rp[k];
-            A[i][k] = f;
+        for (int j = k + 1; j < N; ++j) rk[j] = __shfl(a[j], k, G);
+        if (row && g > k) {
+            const double f = a[k] * rp[k];
+            a[k] = f;
 #pragma unroll
-            for (int j = k + 1; j < N; ++j) A[i][j] = fma(-f, A[k][j], A[i][j]);
+            for (int j = k + 1; j < N; ++j) a[j] = fma(-f, rk[j], a[j]);
         }
     }
-    double Binv[N][N];
+    // column g of the inverse
+    double x[N];
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-        double x[N];
+    for (int i = 0; i < N; ++i) x[i] = i == g ? 1.0 : 0.0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = i == c ? 1.0 : 0.0;
+    for (int k = 0; k < N; ++k)
 #pragma unroll
-        for (int k = 0; k < N; ++k)
+        for (int i = k + 1; i < N; ++i)
+            if (pv[k] == i) {
+                const double t = x[k];
+                x[k] = x[i];
+                x[i] = t;
+            }
 #pragma unroll
-            for (int i = k + 1; i < N; ++i)
-                if (pv[k] == i) {
-                    const double t = x[k];
-                    x[k] = x[i];
-                    x[i] = t;
-                }
+    for (int i = 1; i < N; ++i) {
+        double s = x[i];
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            double s = x[i];
-#pragma unroll
-            for (int kk = 0; kk < i; ++kk) s = fma(-A[i][kk], x[kk], s);
-            x[i] = s;
-        }
-#pragma unroll
-        for (int i = N - 1; i >= 0; --i) {
-            double s = x[i];
-#pragma unroll
-            for (int kk = i + 1; kk < N; ++kk) s = fma(-A[i][kk], x[kk], s);
-            x[i] = s * rp[i];
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) Binv[i][c] = sing ? 0.0 : x[i];
+        for (int kk = 0; kk < i; ++kk) s = fma(-__shfl(a[kk], i, G), x[kk], s);
+        x[i] = s;
     }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        double s = x[i];
+#pragma unroll
+        for (int kk = i + 1; kk < N; ++kk) s = fma(-__shfl(a[kk], i, G), x[kk], s);
+        x[i] = s * rp[i];
+    }
+    if (row) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) tr[wl][i][g] = sing ? 0.0 : x[i];
+    }
+    __syncthreads();
+    if (!row) return;
+    double br[N];                            // row g of the inverse
+#pragma unroll
+    for (int k = 0; k < N; ++k) br[k] = tr[wl][g][k];
+#pragma unroll
+    for (int k = 0; k < N; ++k) Bw[g * N + k] = br[k];
     if (g == 0) {
         if (sing) {
             S.logdet[w] = -INFINITY;
@@ -292,13 +296,8 @@ k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__res
             S.sgn[w] = sg;
         }
     }
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-        if (r % RPW == g)
-#pragma unroll
-            for (int j = 0; j < N; ++j) Bw[r * N + j] = Binv[r][j];
-    // T_V = A^-1 Phi_V, walker-tiled
-    const size_t tb = (size_t)(w / WT) * N * m * WT + (w % WT);
+    // row g of T_V = A^-1 Phi_V, walker-tiled
+    const size_t tb = (size_t)(w / WT) * N * m * WT + (w % WT) + (size_t)g * m * WT;
     for (int p0 = 0; p0 < m; p0 += PB) {
         double pn[PB][N];
         if (p0 + PB < m) {
@@ -310,16 +309,12 @@ k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__res
 #pragma unroll
         for (int u = 0; u < PB; ++u) {
             if (p0 + u >= m) break;
+            double s = 0.0;
 #pragma unroll
-            for (int r = 0; r < N; ++r) {
-                if (r % RPW != g) continue;
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < N; ++k) s = fma(Binv[r][k], ph[u][k], s);
-                const size_t o = tb + ((size_t)r * m + p0 + u) * WT;
-                if (prec == 0) Tg[o] = s;
-                else T32[o] = (float)s;
-            }
+            for (int k = 0; k < N; ++k) s = fma(br[k], ph[u][k], s);
+            const size_t o = tb + (size_t)(p0 + u) * WT;
+            if (prec == 0) Tg[o] = s;
+            else T32[o] = (float)s;
         }
 #pragma unroll
         for (int u = 0; u < PB; ++u)
@@ -330,7 +325,7 @@ k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__res
 
 hipError_t launch_refresh_small(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
                                 const double *orb_in, int32_t *status) {
-    const dim3 grid((unsigned)(((size_t)h.W * RPW + 63) / 64));
+    const dim3 grid((unsigned)(((size_t)h.W * 8 + 63) / 64));
 #define MDE_RS(X)                                                                          \
     case X:                                                                                \
         hipLaunchKernelGGL(k_refresh_small<X>, grid, dim3(64), 0, st, d_inst, spin, orb_in, \
