@@ -104,6 +104,7 @@ struct mde_ctx {
     bool initialized = false;
     bool adjoint_state = false;
     bool R_valid[2] = {false, false};
+    bool coef_gathered = false;    // coef_s holds the context's own coefficients
     bool C_valid[2] = {false, false};
     int pending_e = -1;
     bool pending_fused = false;   // the pending proposal was formed in the determinant kernel
@@ -851,7 +852,10 @@ static mde_status ensure_C(mde_ctx *c, int s) {
 static mde_status full_eval(mde_ctx *c, const double *orb_up, const double *orb_dn,
                             double *log_abs, double *sign, int32_t *status, bool need_n = true) {
     const double *orb[2] = {orb_up, orb_dn};
-    MDE_HIP(c, launch_coef_gather(c->stream, c->d_inst, c->h, c->h.coef));
+    if (!c->coef_gathered) {
+        MDE_HIP(c, launch_coef_gather(c->stream, c->d_inst, c->h, c->h.coef));
+        c->coef_gathered = true;
+    }
     for (int s = 0; s < 2; ++s) {
         if (c->sp[s].n <= 8) {
             MDE_HIP(c, launch_refresh_small(c->stream, c->d_inst, c->h, s, orb[s], status));
@@ -1236,6 +1240,7 @@ mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
                                  hipMemcpyHostToDevice));
         }
     }
+    c->coef_gathered = false;
     MDE_HIP(c, hipMemcpy((void *)c->h.coef, c->coef.data(), sizeof(double) * c->n_det,
                          hipMemcpyHostToDevice));
     c->bound = true;
@@ -1378,6 +1383,7 @@ mde_status mde_eval_tables(mde_ctx *c, const double *T_up, const double *T_dn, c
     if (!T_up || !T_dn || !coef) MDE_FAIL(c, MDE_INVALID, "tables and coefficients required");
     MDE_HIP(c, launch_fill_i32(c->stream, c->h.st, 0, c->W));
     MDE_HIP(c, launch_coef_gather(c->stream, c->d_inst, c->h, coef));
+    c->coef_gathered = false;
     mde_status st = run_values(c, 0, T_up, T_dn);
     if (st) return st;
     st = run_values(c, 1, T_up, T_dn);
