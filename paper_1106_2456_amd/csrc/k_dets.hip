@@ -690,34 +690,69 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
         Vs[idx] = v;
     }
     __syncthreads();
-    // component b = 0..4 of walker lane l: thread (b, l), b = wave, wave + nw;
-    // the walker's 2 x no values are read in groups of 8 loads
+    // The contraction with the walker's new orbital values: with 8 waves,
+    // wave v takes walkers 8v .. 8v + 7, eight lanes each; lane j reads
+    // entries k = j, j + 8, .. of the walker's five rows (eight lanes read 64
+    // contiguous bytes) and the eight partial sums are added across the lane
+    // group in a fixed butterfly.  Other block sizes: thread (b, l), b = wave,
+    // wave + nw, reads the walker's row b.  Component 0 carries a', the
+    // others the gradient and laplacian rows, of opposite sign.
     double ctr[2] = {0.0, 0.0};
     const int w = w0 + lane;
+    if (nw == 8) {
+        const int l8 = wave * 8 + (lane >> 3), j = lane & 7, w8 = w0 + l8;
+        double pb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (w8 < W) {
+            const auto ob = orb + (size_t)w8 * 5 * no;
+            for (int k0 = 0; k0 < no; k0 += 32) {
+                double x[4][5], gk[4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int b = wave + i * nw;
-        if (b < 5 && w < W) {
-            const auto ob = orb + ((size_t)w * 5 + b) * no;
-            double so = 0.0, sv = 0.0;
-            int k = 0;
-            for (; k + 8 <= no; k += 8) {
-                double x[8];
+                for (int u = 0; u < 4; ++u) {
+                    const int k = k0 + j + 8 * u;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = ob[k + u];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int kk = k + u;
-                    if (kk < n) so = fma(x[u], Vs[kk * 64 + lane], so);
-                    else sv = fma(Wall[(kk - n) * 64 + lane], x[u], sv);
+                    for (int bb = 0; bb < 5; ++bb) x[u][bb] = k < no ? ob[bb * no + k] : 0.0;
+                    gk[u] = k < no ? (k < n ? Vs[k * 64 + l8] : -Wall[(k - n) * 64 + l8]) : 0.0;
                 }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int bb = 0; bb < 5; ++bb) pb[bb] = fma(x[u][bb], gk[u], pb[bb]);
             }
-            for (; k < no; ++k) {
-                const double x = ob[k];
-                if (k < n) so = fma(x, Vs[k * 64 + lane], so);
-                else sv = fma(Wall[(k - n) * 64 + lane], x, sv);
+        }
+#pragma unroll
+        for (int bb = 0; bb < 5; ++bb)
+#pragma unroll
+            for (int off = 4; off >= 1; off >>= 1) pb[bb] += __shfl_xor(pb[bb], off, 8);
+        // lane j = b of the group keeps component b (b < 5)
+#pragma unroll
+        for (int bb = 0; bb < 5; ++bb)
+            if (j == bb) ctr[0] = bb == 0 ? pb[bb] : -pb[bb];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int b = wave + i * nw;
+            if (b < 5 && w < W) {
+                const auto ob = orb + ((size_t)w * 5 + b) * no;
+                double so = 0.0, sv = 0.0;
+                int k = 0;
+                for (; k + 8 <= no; k += 8) {
+                    double x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) x[u] = ob[k + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int kk = k + u;
+                        if (kk < n) so = fma(x[u], Vs[kk * 64 + lane], so);
+                        else sv = fma(Wall[(kk - n) * 64 + lane], x[u], sv);
+                    }
+                }
+                for (; k < no; ++k) {
+                    const double x = ob[k];
+                    if (k < n) so = fma(x, Vs[k * 64 + lane], so);
+                    else sv = fma(Wall[(k - n) * 64 + lane], x, sv);
+                }
+                ctr[i] = b == 0 ? so - sv : sv - so;
             }
-            ctr[i] = b == 0 ? so - sv : sv - so;
         }
     }
     __syncthreads();   // Tab, W, V read: the LDS holds the reduction now
@@ -725,9 +760,14 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
     double *red2 = red + (size_t)nw * NSUM * 64;
 #pragma unroll
     for (int q = 0; q < NSUM; ++q) red[((size_t)wave * NSUM + q) * 64 + lane] = acc[q];
+    if (nw == 8) {
+        const int j = lane & 7;
+        if (j < 5) red2[j * 64 + wave * 8 + (lane >> 3)] = ctr[0];
+    } else {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-        if (wave + i * nw < 5) red2[(wave + i * nw) * 64 + lane] = ctr[i];
+        for (int i = 0; i < 2; ++i)
+            if (wave + i * nw < 5) red2[(wave + i * nw) * 64 + lane] = ctr[i];
+    }
     __syncthreads();
     const auto pout = MDE_GW(double, S.partial);
     for (int idx = tid; idx < 64 * NSUM; idx += nthr) {
