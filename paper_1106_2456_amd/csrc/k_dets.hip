@@ -656,6 +656,19 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
     const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
     const int w0 = it.tile * WT;
     const auto orb = MDE_G(double, mv.new_orb);
+    // with 8 waves: the first 32 entries of each of the walker's five rows
+    // for the contraction below, loaded before the W and V sums
+    const int l8 = wave * 8 + (lane >> 3), j8 = lane & 7, w8 = w0 + l8;
+    double x0[4][5];
+    if (nw == 8) {
+        const auto ob = orb + (size_t)(w8 < W ? w8 : w0) * 5 * no;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = j8 + 8 * u;
+#pragma unroll
+            for (int bb = 0; bb < 5; ++bb) x0[u][bb] = (k < no && w8 < W) ? ob[bb * no + k] : 0.0;
+        }
+    }
     __syncthreads();   // all waves done: W final, Tab and c intact
     // (the sums below read all their terms before adding them, in the same
     // order as a plain loop: the reads overlap, the result is unchanged)
@@ -700,7 +713,7 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
     double ctr[2] = {0.0, 0.0};
     const int w = w0 + lane;
     if (nw == 8) {
-        const int l8 = wave * 8 + (lane >> 3), j = lane & 7, w8 = w0 + l8;
+        const int j = j8;
         double pb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         if (w8 < W) {
             const auto ob = orb + (size_t)w8 * 5 * no;
@@ -710,7 +723,8 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
                 for (int u = 0; u < 4; ++u) {
                     const int k = k0 + j + 8 * u;
 #pragma unroll
-                    for (int bb = 0; bb < 5; ++bb) x[u][bb] = k < no ? ob[bb * no + k] : 0.0;
+                    for (int bb = 0; bb < 5; ++bb)
+                        x[u][bb] = k0 == 0 ? x0[u][bb] : (k < no ? ob[bb * no + k] : 0.0);
                     gk[u] = k < no ? (k < n ? Vs[k * 64 + l8] : -Wall[(k - n) * 64 + l8]) : 0.0;
                 }
 #pragma unroll
