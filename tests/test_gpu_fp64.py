@@ -120,6 +120,42 @@ def test_trajectory_batched_walkers_and_state():
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("n", [1, 2, 4, 6, 8])
+def test_refresh_state_small_spins(n):
+    """The refresh of spins with at most 8 electrons (eight lanes per walker,
+    pivoting across the lane group): inverse, log|det| and table after a
+    commit and its refresh, 70 walkers (a partial second tile), against a
+    fresh LU of the final positions."""
+    wl = synth.tiny_system(40 + n, n, n, 6, 60, W=70, n_moves=2)
+    ctx = make_ctx(wl, refresh_every=1)
+    pos = wl.walkers.pos.copy()
+    ou, od = gpu_orbitals(ctx, pos)
+    ctx.init(ou, od)
+    e = int(wl.moves.electron[0])
+    new_r = pos[:, e] + wl.moves.disp[0]
+    ctx.propose(e, ctx.sgauss_eval(ctx.spin_of(e), dev(new_r)))
+    mask = wl.moves.accept_half[0]
+    ctx.accept(e, dev(mask, torch.uint8))      # refresh after every commit
+    acc = mask.astype(bool)
+    pos[acc, e] = new_r[acc]
+    rou, rod = oracle.walker_orbitals(wl.system, pos)
+    worst = 0.0
+    for spin, orb in ((0, rou), (1, rod)):
+        B = ctx.export("inverse", spin).cpu().numpy()
+        ld = ctx.export("logdet", spin).cpu().numpy()
+        T = ctx.export("table", spin).cpu().numpy()
+        for w in range(wl.walkers.W):
+            A = orb[w, :, 0, :n]
+            cond = np.linalg.cond(A)
+            ref_T = np.linalg.solve(A, orb[w, :, 0, n:])
+            e_B = np.abs(B[w] @ A - np.eye(n)).max()
+            e_ld = abs(ld[w] - np.linalg.slogdet(A)[1])
+            e_T = np.abs(T[w] - ref_T).max() / (1.0 + np.abs(ref_T).max())
+            worst = max(worst, e_B / cond, e_ld / cond, e_T / cond)
+            assert e_B <= 1e-11 * cond and e_ld <= 1e-11 * cond and e_T <= 1e-11 * cond, (spin, w)
+    say(f"n={n}: refresh state, worst condition-scaled error {worst:.2e}")
+
+
 def test_sizing_query_after_bind_keeps_state():
     """Regression: a workspace-size query on a bound context must not touch
     its device descriptors (it once replaced them with null pointers)."""
