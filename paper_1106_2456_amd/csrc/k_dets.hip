@@ -1484,7 +1484,8 @@ __device__ __forceinline__ void finish_walker_v(const InstDev &I, const MoveArgs
                                                 const double (&sum)[NSUM], double rho,
                                                 const double (&kap)[4], int st) {
     double ratio, rNp, d[4];
-    if (I.prec == 0) {
+    const int prec = I.prec;
+    if (prec == 0) {
         const double N = sum[0];
         rNp = fma(rho, N, -sum[1]);       // rho N'
         ratio = rNp / N;
@@ -1650,9 +1651,26 @@ __global__ void __launch_bounds__(256) k_post(const InstDev *__restrict__ insts,
 #pragma unroll
         for (int q = 0; q < NSUM; ++q) sum_s[q][l] = sum[q];
     }
-    if (live)
-        for (int p = g; p < no; p += NG) I.newrow[(size_t)w * I.nomax + p] = orb[p];
-    const int st_old = (g == 0 && live) ? I.st[w] : 0;
+    // descriptor fields and the walker's status read before the first store
+    // (a store through a pointer could otherwise alias them: each would be
+    // read again, one round trip later)
+    double *const nrow = I.newrow + (size_t)(live ? w : 0) * I.nomax;
+    const auto rrow_g = MDE_GW(double, I.rrow) + (size_t)t * n * WT + l;
+    const auto cc_g = MDE_GW(double, I.cc) + (size_t)t * n * WT + l;
+    double *const rho_g = I.rho;
+    double *const kap_g = I.kap;
+    int32_t *const st_g = I.st;
+    const int st_old = (g == 0 && live) ? st_g[w] : 0;
+    if (live) {
+        // this thread's quarter of the new orbital row, loaded, then stored
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = g + NG * i < no ? orb[g + NG * i] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (g + NG * i < no) nrow[g + NG * i] = v[i];
+        for (int p = g + NG * 8; p < no; p += NG) nrow[p] = orb[p];
+    }
     __syncthreads();
     if (g != 0 || !live) return;
     // c and r = a'^T A^-1 - e_i^T for the commit (tiled like the tables)
@@ -1660,8 +1678,8 @@ __global__ void __launch_bounds__(256) k_post(const InstDev *__restrict__ insts,
         double r = 0.0;
 #pragma unroll
         for (int h = 0; h < NG; ++h) r += rr_s[h][j][l];
-        MDE_GW(double, I.rrow)[((size_t)t * n + j) * WT + l] = r - (j == row ? 1.0 : 0.0);
-        MDE_GW(double, I.cc)[((size_t)t * n + j) * WT + l] = c_s[j][l];
+        rrow_g[(size_t)j * WT] = r - (j == row ? 1.0 : 0.0);
+        cc_g[(size_t)j * WT] = c_s[j][l];
     }
     double rk[5];
 #pragma unroll
@@ -1670,12 +1688,12 @@ __global__ void __launch_bounds__(256) k_post(const InstDev *__restrict__ insts,
         for (int r = 0; r < n; ++r) v = fma(o_s[b][r][l], c_s[r][l], v);
         rk[b] = v;
     }
-    I.rho[w] = rk[0];
+    rho_g[w] = rk[0];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) I.kap[(size_t)w * 4 + b] = rk[1 + b];
+    for (int b = 0; b < 4; ++b) kap_g[(size_t)w * 4 + b] = rk[1 + b];
     const int bits = (!isfinite(rk[0]) || fabs(rk[0]) < 1e-300) ? 2 : 0;
     const int st = (st_old & ~2) | bits;
-    I.st[w] = st;
+    st_g[w] = st;
     double sum[NSUM];
 #pragma unroll
     for (int q = 0; q < NSUM; ++q) sum[q] = sum_s[q][l];

@@ -939,6 +939,14 @@ k_accept64f(const InstDev *__restrict__ insts, MoveArgs mv, int split, int T8) {
     const int pf = part * NG + g;
     const double nf = pf < no ? nr[pf] : 0.0;
     const double nnew = I.Nnew[w];
+    // the remaining destinations, and the values the first thread updates,
+    // also before any store (a store could alias the descriptor's fields)
+    double *const Phi = S.Phi + ((size_t)w * n + row) * no;
+    double *const ld_g = S.logdet;
+    double *const sg_g = S.sgn;
+    double *const nold_g = I.Nold;
+    const bool first = part == 0 && g == 0;
+    const double ld0 = first ? ld_g[w] : 0.0, sg0 = first ? sg_g[w] : 0.0;
     if (!acc) return;
     const double ir = 1.0 / rho;
 #pragma unroll
@@ -976,12 +984,11 @@ k_accept64f(const InstDev *__restrict__ insts, MoveArgs mv, int split, int T8) {
         }
     }
     // orbital row of the moved electron
-    double *Phi = S.Phi + ((size_t)w * n + row) * no;
     for (int p = pf; p < no; p += split * NG) Phi[p] = p == pf ? nf : nr[p];
-    if (part == 0 && g == 0) {
-        S.logdet[w] += log(fabs(rho));
-        if (rho < 0.0) S.sgn[w] = -S.sgn[w];
-        I.Nold[w] = nnew;
+    if (first) {
+        ld_g[w] = ld0 + log(fabs(rho));
+        if (rho < 0.0) sg_g[w] = -sg0;
+        nold_g[w] = nnew;
     }
 }
 
