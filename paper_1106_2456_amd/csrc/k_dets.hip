@@ -1672,15 +1672,19 @@ __global__ void __launch_bounds__(256) k_post(const InstDev *__restrict__ insts,
         for (int p = g + NG * 8; p < no; p += NG) nrow[p] = orb[p];
     }
     __syncthreads();
-    if (g != 0 || !live) return;
-    // c and r = a'^T A^-1 - e_i^T for the commit (tiled like the tables)
-    for (int j = 0; j < n; ++j) {
-        double r = 0.0;
+    if (!live || g > 1) return;
+    if (g == 1) {
+        // c and r = a'^T A^-1 - e_i^T for the commit (tiled like the tables)
+        for (int j = 0; j < n; ++j) {
+            double r = 0.0;
 #pragma unroll
-        for (int h = 0; h < NG; ++h) r += rr_s[h][j][l];
-        rrow_g[(size_t)j * WT] = r - (j == row ? 1.0 : 0.0);
-        cc_g[(size_t)j * WT] = c_s[j][l];
+            for (int h = 0; h < NG; ++h) r += rr_s[h][j][l];
+            rrow_g[(size_t)j * WT] = r - (j == row ? 1.0 : 0.0);
+            cc_g[(size_t)j * WT] = c_s[j][l];
+        }
+        return;
     }
+    // thread 0 of the walker: rho, kappa and the results
     double rk[5];
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
