@@ -205,3 +205,33 @@ def test_graph_replay_matches_eager():
                 for a, b in zip(outs[k][:3], r[:3]):
                     assert torch.equal(a, b), (rep, k)
             _ = torch.ones(10, device="cuda").sum().item()   # eager work between replays
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_profiled_repeats_leave_results_unchanged(precision):
+    """A profiled proposal issues the determinant kernel several times back to
+    back between its events; the results must equal an unprofiled twin's."""
+    wl = synth.water_like(2, W=128, n_det=800, n_moves=4)
+    s = wl.system
+    ctxs = [make_ctx(wl, precision=precision) for _ in range(2)]
+    pos = wl.walkers.pos.copy()
+    for c in ctxs:
+        ou, od = gpu_orbitals(c, pos)
+        c.init(ou, od)
+    ctxs[0].profile_enable(16, 4)
+    for k in range(4):
+        e = int(wl.moves.electron[k])
+        no = ctxs[0].sgauss_eval(ctxs[0].spin_of(e), dev(pos[:, e] + wl.moves.disp[k]))
+        mask = dev(wl.moves.accept_half[k], torch.uint8)
+        r0 = ctxs[0].propose(e, no)
+        r1 = ctxs[1].propose(e, no)
+        for a, b in zip(r0[:3], r1[:3]):
+            assert torch.equal(a, b), k
+        for c in ctxs:
+            c.accept(e, mask)
+    torch.cuda.synchronize()
+    ms, n = ctxs[0].profile_read()
+    ctxs[0].profile_disable()
+    say(f"{precision}: {n} profiled launches, {ms / max(n, 1) * 1e3:.1f} us each")
+    assert n == 16 and ms > 0.0
+
