@@ -16,7 +16,10 @@ Metric: walker.det/s = walkers x determinants x moves / time.  The JSON line
 also carries the roofline of the determinant kernel (bound by HBM: it streams
 every walker's CI weights once per move; its FP64 vector-ALU figure beside),
 the CPU oracle timed on a bounded sample of the same workload, and the other
-precision forms.
+precision forms.  `--rows adjoint,uneven` adds two more rows of the path
+under "rows": the adjoint (forward from the tables + backward, 1024 walkers,
+FP64, with the oracle timed beside it) and 64 uneven instances moved
+together in one group launch.
 """
 from __future__ import annotations
 
@@ -242,6 +245,126 @@ def cpu_baseline(wl, target_seconds=12.0):
                        f"(full-LU oracle, {dt:.1f} s)")
 
 
+def run_adjoint(steps, warmup, cpu=True):
+    """Forward ln|sum_I c_I det S_up det S_dn| from the walkers' own tables and
+    its adjoint (grad_c summed over walkers, grad_T per walker), FP64, on the
+    water-like system with 1024 walkers; one step = eval_tables + backward."""
+    import torch
+    wl = synth_mod().water_like(4)
+    s = wl.system
+    W = wl.walkers.W
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = build_context(wl, "fp64", stream, refresh_every=None)
+        pos = torch.as_tensor(wl.walkers.pos, device="cuda")
+        nu = s.n_elec[0]
+        ctx.init(ctx.sgauss_eval(0, pos[:, :nu].contiguous()), ctx.sgauss_eval(1, pos[:, nu:].contiguous()))
+        Tu = ctx.export("table", 0).clone()
+        Td = ctx.export("table", 1).clone()
+        coef = torch.as_tensor(s.coef, device="cuda")
+        go = torch.as_tensor(np.random.default_rng(44).normal(0, 1, W), device="cuda")
+
+        def step():
+            ctx.eval_tables(Tu, Td, coef)
+            ctx.backward(go)
+
+        for _ in range(max(warmup, 1)):
+            step()
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    out = dict(value=W * s.n_det / (ms * 1e-3), unit="walker.det/s", ms_per_step=ms,
+               workload=f"water-like, {W} walkers, {s.n_det} determinants, FP64; "
+                        "step = forward from the tables + backward (grad_c, grad_T)")
+    if cpu:
+        import oracle
+        k = min(W, 256)
+        tu, td = Tu[:k].cpu().numpy(), Td[:k].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.tables(s, tu, td)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=k * s.n_det / dt, unit="walker.det/s",
+                                   cores=oracle.num_threads(), kind="oracle",
+                                   sample=f"{k} walkers, forward + adjoint by full LU ({dt:.2f} s)")
+    return out
+
+
+def run_uneven(steps, warmup, n_moves=4):
+    """64 instances of uneven size (n = 5..64 electrons per spin, m = 4n,
+    100..200 000 determinants, 256 walkers each) moved together: one step =
+    one group proposal + commit of one electron in every instance, FP64."""
+    import torch
+    from paper_1106_2456_amd import Context, Group
+    log("uneven: generating 64 instances")
+    wls = synth_mod().uneven_instances(W=256, n_moves=n_moves)
+    ctxs = []
+    for w in wls:
+        sy = w.system
+        mo = max(int(sy.exc[0].orders().max()), int(sy.exc[1].orders().max()), 1)
+        c = Context(sy.n_elec, sy.n_orb, 256, max_order=mo, precision="fp64")
+        c.set_expansion(sy.exc[0], sy.exc[1], sy.coef, sy.det_up, sy.det_dn)
+        for sp in (0, 1):
+            c.set_basis(sp, sy.centres, sy.expo, sy.mo_spin(sp))
+        ctxs.append(c)
+    grp = Group(ctxs, [256] * len(wls))
+    moves = []
+    for c, w in zip(ctxs, wls):
+        pos = torch.as_tensor(w.walkers.pos, device="cuda")
+        nu = w.system.n_elec[0]
+        c.init(c.sgauss_eval(0, pos[:, :nu].contiguous()), c.sgauss_eval(1, pos[:, nu:].contiguous()))
+    for k in range(n_moves):
+        es, news, masks = [], [], []
+        for c, w in zip(ctxs, wls):
+            e = int(w.moves.electron[k])
+            r = torch.as_tensor(w.walkers.pos[:, e] + w.moves.disp[k], device="cuda")
+            es.append(e)
+            news.append(c.sgauss_eval(c.spin_of(e), r.contiguous()))
+            masks.append(torch.as_tensor(w.moves.accept_half[k], dtype=torch.uint8, device="cuda"))
+        moves.append((es, news, masks))
+    outs = [(torch.empty(256, dtype=torch.float64, device="cuda"),
+             torch.empty((256, 3), dtype=torch.float64, device="cuda"),
+             torch.empty(256, dtype=torch.float64, device="cuda"),
+             torch.zeros(256, dtype=torch.int32, device="cuda")) for _ in wls]
+    stream = grp.stream
+    torch.cuda.synchronize()
+
+    def step(k):
+        es, news, masks = moves[k % n_moves]
+        grp.propose(es, news, outs)
+        grp.accept(es, masks)
+
+    for k in range(max(warmup, 1)):
+        step(k)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(steps):
+        step(k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    wdets = sum(256 * w.system.n_det for w in wls)
+    st = torch.stack([o[3] for o in outs]).cpu().numpy()
+    return dict(value=wdets / (ms * 1e-3), unit="walker.det/s", ms_per_step=ms,
+                walker_dets_per_step=wdets, status_bits=int(np.bitwise_or.reduce(st.ravel())),
+                plan=ctxs[0].get_plan(0),
+                workload="64 uneven instances x 256 walkers (n 5..64 per spin, m = 4n, "
+                         "N_det 1e2..2e5 log-uniform), FP64; step = one group proposal + "
+                         "commit, eager launches")
+
+
+def synth_mod():
+    import synth
+    return synth
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +376,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--repeat", type=int, default=8,
                     help="back-to-back determinant-kernel launches per HIP event pair")
+    ap.add_argument("--rows", default="",
+                    help="also measure these other rows of the path (comma list of "
+                         "adjoint, uneven); reported under 'rows'")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the forms, run a plain device copy (torch.neg, out=) of this many "
                          "MiB three times: the known-size reference for the HBM byte counters")
@@ -278,6 +404,15 @@ def main():
             f"det kernel {r['det_avg_us']:.1f} us ({r['det_gbs']:.0f} GB/s, {r['det_tflops']:.2f} TFLOP/s; "
             f"{r['det_single_us']:.1f} us one launch per event pair) plan {r['plan'][0]}")
         forms[f] = r
+    rows = {}
+    for r in [x for x in args.rows.split(",") if x]:
+        if r == "adjoint":
+            rows[r] = run_adjoint(args.steps, args.warmup, cpu=not args.no_cpu)
+        elif r == "uneven":
+            rows[r] = run_uneven(min(args.steps, 10), args.warmup)
+        else:
+            raise SystemExit(f"unknown row {r!r}")
+        log(f"{r}: {rows[r]['ms_per_step']:.3f} ms/step  {rows[r]['value']:.3e} walker.det/s")
     if args.copy_mib > 0:
         x = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
@@ -325,6 +460,8 @@ def main():
                                            "plan")}
                   for k, v in forms.items()},
     }
+    if rows:
+        out["rows"] = rows
     print(json.dumps(out))
 
 

@@ -24,33 +24,42 @@ __global__ void k_gw(const InstDev *__restrict__ insts, const double *__restrict
     if (w < I.W) I.Lnew[w] = go[w] / I.Nold[w];
 }
 
-// grad_c[I] = sum_w gw[w] R_up[w][u(I)] R_dn[w][d(I)]; one wave per up
-// excitation u, lanes over walkers, fixed butterfly reduction.
+// grad_c[I] = sum_w gw[w] R_up[w][u(I)] R_dn[w][d(I)]; one wave per CI term
+// k (terms are stored grouped by their up excitation: u(k) is found by
+// bisection of the segment offsets), lanes over walkers, fixed butterfly
+// reduction.  A wave per term keeps the work even: the terms of one
+// excitation (the reference's above all) are spread over many waves.
 __global__ void k_grad_coef(const InstDev *__restrict__ insts, double *__restrict__ grad_coef) {
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[0];
     const SpinDev &O = I.s[1];
     const int lane = threadIdx.x & 63;
-    const int u = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (u >= S.U) return;
-    const int a = S.ci_seg[u], b = S.ci_seg[u + 1];
-    const int WT = S.WT, W = I.W;
-    for (int k = a; k < b; ++k) {
-        const int d = S.ci_other[k];
-        double s = 0.0;
-        for (int w0 = 0; w0 < W; w0 += 64) {
-            const int w = w0 + lane;
-            if (w < W) {
-                const int t = w / WT, wl = w - t * WT;
-                const double ru = S.R[((size_t)t * S.U + u) * WT + wl];
-                const double rd = O.R[((size_t)t * O.U + d) * WT + wl];
-                s = fma(I.Lnew[w] * ru, rd, s);
-            }
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (lane == 0) grad_coef[S.ci_idx[k]] = s;
+    const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const int32_t *seg = S.ci_seg;
+    if (k >= seg[S.U]) return;
+    // largest u with seg[u] <= k: its segment [seg[u], seg[u + 1]) holds k
+    int lo = 0, hi = S.U;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= k) lo = mid;
+        else hi = mid;
     }
+    const int u = lo;
+    const int d = S.ci_other[k];
+    const int WT = S.WT, W = I.W;
+    double s = 0.0;
+    for (int w0 = 0; w0 < W; w0 += 64) {
+        const int w = w0 + lane;
+        if (w < W) {
+            const int t = w / WT, wl = w - t * WT;
+            const double ru = S.R[((size_t)t * S.U + u) * WT + wl];
+            const double rd = O.R[((size_t)t * O.U + d) * WT + wl];
+            s = fma(I.Lnew[w] * ru, rd, s);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) grad_coef[S.ci_idx[k]] = s;
 }
 
 template <int K>
@@ -85,9 +94,11 @@ __device__ double cof_entry_generic(const double *tabs, const uint4 &ex, int k, 
     return y[l];
 }
 
-// grad_T_sigma: one block per walker tile; the tile's table in LDS; lanes
-// (slot, walker) walk table entries and their inverted lists.
-__global__ void __launch_bounds__(1024)
+// grad_T_sigma: blocks (walker tile, part of the table entries); the tile's
+// table in LDS; lanes (slot, walker) walk table entries and their inverted
+// lists.  Spreading a tile's entries over gridDim.y blocks fills the chip
+// even when there are few tiles.
+__global__ void __launch_bounds__(256)
 k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__ Tin,
          double *__restrict__ grad_T) {
     const InstDev &I = insts[0];
@@ -106,7 +117,7 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
     const int w = t * WT + wl;
     const double gw = (w < W) ? I.Lnew[w] : 0.0;
     const double *__restrict__ Cb = S.C + (size_t)t * S.U * WT;
-    for (int e = slot; e < nm; e += nslot) {
+    for (int e = blockIdx.y * nslot + slot; e < nm; e += nslot * (int)gridDim.y) {
         const int a = S.inv_off[e], b = S.inv_off[e + 1];
         double acc = 0.0;
         for (int q = a; q < b; ++q) {
@@ -137,8 +148,9 @@ hipError_t launch_backward(hipStream_t st, const InstDev *d_inst, const InstDev 
     if (e != hipSuccess) return e;
     if (grad_coef) {
         const int wpb = 4;
-        hipLaunchKernelGGL(k_grad_coef, dim3((h.s[0].U + wpb - 1) / wpb), dim3(64 * wpb), 0, st,
-                           d_inst, grad_coef);
+        const int64_t terms = h.n_det;
+        hipLaunchKernelGGL(k_grad_coef, dim3((unsigned)((terms + wpb - 1) / wpb)), dim3(64 * wpb), 0,
+                           st, d_inst, grad_coef);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -148,12 +160,13 @@ hipError_t launch_backward(hipStream_t st, const InstDev *d_inst, const InstDev 
         if (!gT[s]) continue;
         const SpinDev &S = h.s[s];
         const size_t lds = sizeof(double) * (size_t)S.n * S.m * S.WTP;
-        const int threads = S.WT >= 64 ? 1024 : 256;
+        const int threads = 256, nslot = threads / S.WT;
+        const int parts = (S.n * S.m + nslot - 1) / nslot;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)k_grad_T,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles), dim3(threads), lds, st, d_inst, s, Tin[s],
-                           gT[s]);
+        hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, parts), dim3(threads), lds, st, d_inst, s,
+                           Tin[s], gT[s]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
