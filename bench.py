@@ -421,6 +421,10 @@ def main():
         torch.cuda.synchronize()
         log(f"copy reference: 3 x torch.neg over {args.copy_mib} MiB (read + write each)")
         del x, y
+    if not forms:
+        # rows only (e.g. `--forms "" --rows adjoint` under a profiler)
+        print(json.dumps({"rows": rows}))
+        return
     head = forms.get("fp64") or next(iter(forms.values()))
     cpu = None if args.no_cpu else cpu_baseline(wl)
     achieved = head["det_gbs"]

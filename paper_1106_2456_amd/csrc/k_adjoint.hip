@@ -94,47 +94,52 @@ __device__ double cof_entry_generic(const double *tabs, const uint4 &ex, int k, 
     return y[l];
 }
 
-// grad_T_sigma: blocks (walker tile, part of the table entries); the tile's
-// table in LDS; lanes (slot, walker) walk table entries and their inverted
-// lists.  Spreading a tile's entries over gridDim.y blocks fills the chip
-// even when there are few tiles.
+// grad_T_sigma: block (walker tile, table entry); the tile's table in LDS;
+// the block's waves (lanes over walkers) take contiguous pieces of the
+// entry's inverted list, and their sums are added in wave order.
 __global__ void __launch_bounds__(256)
 k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__ Tin,
          double *__restrict__ grad_T) {
+    __shared__ double red[256];
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[spin];
     const int n = S.n, m = S.m, WT = S.WT, WTP = S.WTP, W = I.W;
-    const int t = blockIdx.x;
+    const int t = blockIdx.x, e = blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wl = tid % WT, slot = tid / WT, nslot = nthr / WT;
     extern __shared__ double tabs[];
     const int nm = n * m;
     for (int idx = tid; idx < nm * WT; idx += nthr) {
-        const int e = idx % nm, l = idx / nm, w = t * WT + l;
-        tabs[e * WTP + l] = (w < W) ? Tin[(size_t)w * nm + e] : 0.0;
+        const int ee = idx % nm, l = idx / nm, w = t * WT + l;
+        tabs[ee * WTP + l] = (w < W) ? Tin[(size_t)w * nm + ee] : 0.0;
     }
     __syncthreads();
     const int w = t * WT + wl;
-    const double gw = (w < W) ? I.Lnew[w] : 0.0;
     const double *__restrict__ Cb = S.C + (size_t)t * S.U * WT;
-    for (int e = blockIdx.y * nslot + slot; e < nm; e += nslot * (int)gridDim.y) {
-        const int a = S.inv_off[e], b = S.inv_off[e + 1];
-        double acc = 0.0;
-        for (int q = a; q < b; ++q) {
-            const int code = S.inv_ent[q];
-            const int u = code >> 10, k = (code >> 6) & 15, j = (code >> 3) & 7, l = code & 7;
-            const uint4 ex = S.ex[u];
-            double cf;
-            switch (k) {
-                case 1: cf = 1.0; break;
-                case 2: cf = cof_entry<2>(tabs, ex, m, WTP, wl, j, l); break;
-                case 3: cf = cof_entry<3>(tabs, ex, m, WTP, wl, j, l); break;
-                case 4: cf = cof_entry<4>(tabs, ex, m, WTP, wl, j, l); break;
-                default: cf = cof_entry_generic(tabs, ex, k, m, WTP, wl, j, l); break;
-            }
-            acc = fma(Cb[(size_t)u * WT + wl], cf, acc);
+    const int a = S.inv_off[e], b = S.inv_off[e + 1];
+    const int per = (b - a + nslot - 1) / nslot;
+    const int qa = a + slot * per, qb = min(b, qa + per);
+    double acc = 0.0;
+    for (int q = qa; q < qb; ++q) {
+        const int code = S.inv_ent[q];
+        const int u = code >> 10, k = (code >> 6) & 15, j = (code >> 3) & 7, l = code & 7;
+        const uint4 ex = S.ex[u];
+        double cf;
+        switch (k) {
+            case 1: cf = 1.0; break;
+            case 2: cf = cof_entry<2>(tabs, ex, m, WTP, wl, j, l); break;
+            case 3: cf = cof_entry<3>(tabs, ex, m, WTP, wl, j, l); break;
+            case 4: cf = cof_entry<4>(tabs, ex, m, WTP, wl, j, l); break;
+            default: cf = cof_entry_generic(tabs, ex, k, m, WTP, wl, j, l); break;
         }
-        if (w < W) grad_T[(size_t)w * nm + e] = gw * acc;
+        acc = fma(Cb[(size_t)u * WT + wl], cf, acc);
+    }
+    red[slot * WT + wl] = acc;
+    __syncthreads();
+    if (slot == 0 && w < W) {
+        double sum = 0.0;
+        for (int v = 0; v < nslot; ++v) sum += red[v * WT + wl];
+        grad_T[(size_t)w * nm + e] = I.Lnew[w] * sum;
     }
 }
 
@@ -160,12 +165,11 @@ hipError_t launch_backward(hipStream_t st, const InstDev *d_inst, const InstDev 
         if (!gT[s]) continue;
         const SpinDev &S = h.s[s];
         const size_t lds = sizeof(double) * (size_t)S.n * S.m * S.WTP;
-        const int threads = 256, nslot = threads / S.WT;
-        const int parts = (S.n * S.m + nslot - 1) / nslot;
+        if (S.n * S.m > 65535) return hipErrorInvalidValue;
         if (lds > 65536)
             (void)hipFuncSetAttribute((const void *)k_grad_T,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, parts), dim3(threads), lds, st, d_inst, s,
+        hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, S.n * S.m), dim3(256), lds, st, d_inst, s,
                            Tin[s], gT[s]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
