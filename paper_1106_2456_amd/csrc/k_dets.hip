@@ -109,11 +109,12 @@ __device__ double det_one_generic(int k, const uint4 &ex, const TT *__restrict__
     return dd;
 }
 
-// Loop over the item's excitations (slot-strided); the CI weight of the next
-// excitation is loaded while the current one is evaluated.
+// Loop over the item's excitations (slot-strided; records [u0, u1) read from
+// global memory); the CI weight of the next excitation is loaded while the
+// current one is evaluated.
 template <int K, typename TT, int MODE, int WT>
 __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
-                                         const uint4 *__restrict__ exl, const TT *tabs,
+                                         const uint4 *__restrict__ recs, const TT *tabs,
                                          const TT *gs, const TT *cs, int wl, int slot, int nslot,
                                          double acc[NSUM]) {
     const int len = it.u1 - it.u0;
@@ -125,7 +126,7 @@ __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
     double Cn = 0.0;
     if (MODE == DM_PROPOSE && j < len) Cn = Cb[(size_t)j * WT + wl];
     for (; j < len; j += nslot) {
-        const uint4 ex = exl[j];
+        const uint4 ex = recs[j];
         const double Cu = Cn;
         if (MODE == DM_PROPOSE && j + nslot < len) Cn = Cb[(size_t)(j + nslot) * WT + wl];
         double R;
@@ -1058,13 +1059,12 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
         TT *cs = gs + NE * m * WTP;
         const int w0 = it.tile * WT;
         const int nm = n * m;
-        // ---- stage the excitation records and the walker tile's tables ----
-        {
-            // records as 4 x 32-bit words (global loads)
-            uint32_t *exw = reinterpret_cast<uint32_t *>(exl);
-            const auto exg = MDE_G(uint32_t, S.ex) + (size_t)it.u0 * 4;
-            stage_rows<1>(exw, exg, (it.u1 - it.u0) * 4, 1, tid, nthr);
-        }
+        // ---- stage the walker tile's tables ----
+        // (the lanes read their excitation records straight from global
+        // memory, where consecutive slots read consecutive records: no LDS
+        // for records, so an item may span a whole order however large the
+        // tables are)
+        const uint4 *recs = S.ex + it.u0;
         // tables are stored walker-tiled ([tile][e][WT]): straight copies into
         // the padded LDS rows, no index division
         if (MODE == DM_PROPOSE) {
@@ -1097,11 +1097,11 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
         __syncthreads();
         double acc[NSUM] = {0, 0, 0, 0, 0, 0};
         switch (it.order) {
-            case 1: det_loop<1, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-            case 2: det_loop<2, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-            case 3: det_loop<3, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-            case 4: det_loop<4, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
-            default: det_loop<0, TT, MODE, WT>(it, S, exl, tabs, gs, cs, wl, slot, nslot, acc); break;
+            case 1: det_loop<1, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
+            case 2: det_loop<2, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
+            case 3: det_loop<3, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
+            case 4: det_loop<4, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
+            default: det_loop<0, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
         }
         __syncthreads();   // tables no longer needed: reuse LDS for the reduction
         if (MODE == DM_PROPOSE) {

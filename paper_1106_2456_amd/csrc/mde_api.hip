@@ -286,8 +286,8 @@ static int dense_unit(const SpinHost &s, int k) {
 // tiles the dense block needs none and is not part of [u0, u1))
 static int item_records(const SpinHost &s, int u0, int u1, int WT) {
     (void)s;
-    (void)WT;
-    return u1 - u0;
+    // only 64-walker tiles stage their records in LDS
+    return WT == 64 ? u1 - u0 : 0;
 }
 
 // boundaries of nslot ranges of about equal cost over [u0, u1)
@@ -455,8 +455,9 @@ static ItemQueues build_items(const SpinHost &s, int W, int WT, int item_exc, in
             for (int k = 1; k <= s.max_order; ++k) {
                 const int a = s.order_start[k], b = s.order_start[k + 1];
                 if (b <= a) continue;
-                int chunk = (int)std::lround(item_exc * order_cost(2) / order_cost(k));
-                chunk = std::min(std::max(chunk, nslot), ITEM_MAX);
+                // (records are read from global memory: no capacity limit)
+                double want = std::lround((double)item_exc * order_cost(2) / order_cost(k));
+                int chunk = (int)std::min(std::max(want, (double)nslot), (double)(b - a));
                 for (int u = a; u < b; u += chunk) {
                     WorkItem it{};
                     it.inst = 0;
