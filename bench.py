@@ -19,7 +19,7 @@ the CPU oracle timed on a bounded sample of the same workload, and the other
 precision forms.  `--rows adjoint,uneven` adds two more rows of the path
 under "rows": the adjoint (forward from the tables + backward, 1024 walkers,
 FP64, with the oracle timed beside it) and 64 uneven instances moved
-together in one group launch.
+together, one group launch per walker-tile size.
 """
 from __future__ import annotations
 
@@ -298,7 +298,8 @@ def run_adjoint(steps, warmup, cpu=True):
 def run_uneven(steps, warmup, n_moves=4):
     """64 instances of uneven size (n = 5..64 electrons per spin, m = 4n,
     100..200 000 determinants, 256 walkers each) moved together: one step =
-    one group proposal + commit of one electron in every instance, FP64."""
+    a proposal + commit of one electron in every instance, issued as one
+    group launch per walker-tile size, FP64."""
     import torch
     from paper_1106_2456_amd import Context, Group
     log("uneven: generating 64 instances")
@@ -312,7 +313,9 @@ def run_uneven(steps, warmup, n_moves=4):
         for sp in (0, 1):
             c.set_basis(sp, sy.centres, sy.expo, sy.mo_spin(sp))
         ctxs.append(c)
-    grp = Group(ctxs, [256] * len(wls))
+    # one group launch per walker-tile size (the instances whose tables fit
+    # wide tiles keep them)
+    groups = Group.by_tile(ctxs, [256] * len(wls))
     moves = []
     for c, w in zip(ctxs, wls):
         pos = torch.as_tensor(w.walkers.pos, device="cuda")
@@ -331,13 +334,14 @@ def run_uneven(steps, warmup, n_moves=4):
              torch.empty((256, 3), dtype=torch.float64, device="cuda"),
              torch.empty(256, dtype=torch.float64, device="cuda"),
              torch.zeros(256, dtype=torch.int32, device="cuda")) for _ in wls]
-    stream = grp.stream
+    stream = groups[0][0].stream
     torch.cuda.synchronize()
 
     def step(k):
         es, news, masks = moves[k % n_moves]
-        grp.propose(es, news, outs)
-        grp.accept(es, masks)
+        for g, idx in groups:
+            g.propose([es[i] for i in idx], [news[i] for i in idx], [outs[i] for i in idx])
+            g.accept([es[i] for i in idx], [masks[i] for i in idx])
 
     for k in range(max(warmup, 1)):
         step(k)
@@ -354,10 +358,10 @@ def run_uneven(steps, warmup, n_moves=4):
     st = torch.stack([o[3] for o in outs]).cpu().numpy()
     return dict(value=wdets / (ms * 1e-3), unit="walker.det/s", ms_per_step=ms,
                 walker_dets_per_step=wdets, status_bits=int(np.bitwise_or.reduce(st.ravel())),
-                plan=ctxs[0].get_plan(0),
+                tiles={str(ctxs[idx[0]].get_plan(0)["walker_tile"]): len(idx) for _, idx in groups},
                 workload="64 uneven instances x 256 walkers (n 5..64 per spin, m = 4n, "
-                         "N_det 1e2..2e5 log-uniform), FP64; step = one group proposal + "
-                         "commit, eager launches")
+                         "N_det 1e2..2e5 log-uniform), FP64; step = one proposal + commit "
+                         "of every instance, one group launch per walker-tile size, eager")
 
 
 def synth_mod():

@@ -307,6 +307,22 @@ class Group:
             c.bind(W)
         return wt
 
+    @staticmethod
+    def by_tile(ctxs: Sequence[Context], Ws: Sequence[int]):
+        """Unbound contexts split by their default walker tile (the smaller of
+        their two spins'): one group, hence one launch, per tile size, so that
+        instances with small tables keep wide tiles instead of all taking the
+        narrowest.  Returns [(group, positions of its contexts in ctxs)]."""
+        classes = {}
+        for i, c in enumerate(ctxs):
+            wt = min(c.get_plan(0)["walker_tile"], c.get_plan(1)["walker_tile"])
+            classes.setdefault(wt, []).append(i)
+        out = []
+        for wt in sorted(classes, reverse=True):
+            idx = classes[wt]
+            out.append((Group([ctxs[i] for i in idx], [Ws[i] for i in idx]), idx))
+        return out
+
     def __init__(self, ctxs: Sequence[Context], Ws: Optional[Sequence[int]] = None):
         if Ws is not None:
             Group.prepare(ctxs, Ws)

@@ -116,13 +116,18 @@ def test_adjoint_deterministic():
         assert np.array_equal(a, b)
 
 
-def test_group_matches_oracle_and_single_contexts():
+@pytest.mark.parametrize("by_tile", [False, True])
+def test_group_matches_oracle_and_single_contexts(by_tile):
     from paper_1106_2456_amd import Group
     wls = [synth.water_like(2, W=40, n_det=600, n_moves=6),
            synth.tiny_system(21, 3, 3, 9, 150, W=33, n_moves=6),
            synth.molecular(3, W=5, n_det=300, n_moves=6, n=12, m=40, nb=64, n_nuc=6, box=6.0)]
     ctxs = [make_ctx(w, bind=False) for w in wls]
-    grp = Group(ctxs, [w.walkers.W for w in wls])
+    Ws = [w.walkers.W for w in wls]
+    if by_tile:
+        groups = Group.by_tile(ctxs, Ws)
+    else:
+        groups = [(Group(ctxs, Ws), list(range(len(ctxs))))]
     plans = [c.get_plan(0) for c in ctxs]
     say("group plans", plans)
     # twins with the same plan, run one at a time
@@ -148,8 +153,9 @@ def test_group_matches_oracle_and_single_contexts():
                          torch.empty(c.W, dtype=torch.float64, device="cuda"),
                          torch.zeros(c.W, dtype=torch.int32, device="cuda")))
             masks.append(dev(w.moves.accept_half[k], torch.uint8))
-        grp.propose(es, news, outs)
-        grp.accept(es, masks)
+        for grp, idx in groups:
+            grp.propose([es[i] for i in idx], [news[i] for i in idx], [outs[i] for i in idx])
+            grp.accept([es[i] for i in idx], [masks[i] for i in idx])
         for i, (t, w, p) in enumerate(zip(twins, wls, pos)):
             r1 = t.propose(es[i], news[i])
             t.accept(es[i], masks[i])
