@@ -120,10 +120,21 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
     const int per = (b - a + nslot - 1) / nslot;
     const int qa = a + slot * per, qb = min(b, qa + per);
     double acc = 0.0;
+    // the next list entry, its record and its CI weight are loaded while the
+    // current cofactor is formed
+    int code_n = qa < qb ? S.inv_ent[qa] : 0;
+    uint4 ex_n = qa < qb ? S.ex[code_n >> 10] : make_uint4(0, 0, 0, 0);
+    double cw_n = qa < qb ? Cb[(size_t)(code_n >> 10) * WT + wl] : 0.0;
     for (int q = qa; q < qb; ++q) {
-        const int code = S.inv_ent[q];
-        const int u = code >> 10, k = (code >> 6) & 15, j = (code >> 3) & 7, l = code & 7;
-        const uint4 ex = S.ex[u];
+        const int code = code_n;
+        const uint4 ex = ex_n;
+        const double cw = cw_n;
+        if (q + 1 < qb) {
+            code_n = S.inv_ent[q + 1];
+            ex_n = S.ex[code_n >> 10];
+            cw_n = Cb[(size_t)(code_n >> 10) * WT + wl];
+        }
+        const int k = (code >> 6) & 15, j = (code >> 3) & 7, l = code & 7;
         double cf;
         switch (k) {
             case 1: cf = 1.0; break;
@@ -132,7 +143,7 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
             case 4: cf = cof_entry<4>(tabs, ex, m, WTP, wl, j, l); break;
             default: cf = cof_entry_generic(tabs, ex, k, m, WTP, wl, j, l); break;
         }
-        acc = fma(Cb[(size_t)u * WT + wl], cf, acc);
+        acc = fma(cw, cf, acc);
     }
     red[slot * WT + wl] = acc;
     __syncthreads();
