@@ -295,11 +295,11 @@ def run_adjoint(steps, warmup, cpu=True):
     return out
 
 
-def run_uneven(steps, warmup, n_moves=4):
+def run_uneven(steps, warmup, n_moves=4, precision="fp64"):
     """64 instances of uneven size (n = 5..64 electrons per spin, m = 4n,
     100..200 000 determinants, 256 walkers each) moved together: one step =
     a proposal + commit of one electron in every instance, issued as one
-    group launch per walker-tile size, FP64."""
+    group launch per walker-tile size (FP64, or the mixed form)."""
     import torch
     from paper_1106_2456_amd import Context, Group
     log("uneven: generating 64 instances")
@@ -308,7 +308,7 @@ def run_uneven(steps, warmup, n_moves=4):
     for w in wls:
         sy = w.system
         mo = max(int(sy.exc[0].orders().max()), int(sy.exc[1].orders().max()), 1)
-        c = Context(sy.n_elec, sy.n_orb, 256, max_order=mo, precision="fp64")
+        c = Context(sy.n_elec, sy.n_orb, 256, max_order=mo, precision=precision)
         c.set_expansion(sy.exc[0], sy.exc[1], sy.coef, sy.det_up, sy.det_dn)
         for sp in (0, 1):
             c.set_basis(sp, sy.centres, sy.expo, sy.mo_spin(sp))
@@ -360,8 +360,8 @@ def run_uneven(steps, warmup, n_moves=4):
                 walker_dets_per_step=wdets, status_bits=int(np.bitwise_or.reduce(st.ravel())),
                 tiles={str(ctxs[idx[0]].get_plan(0)["walker_tile"]): len(idx) for _, idx in groups},
                 workload="64 uneven instances x 256 walkers (n 5..64 per spin, m = 4n, "
-                         "N_det 1e2..2e5 log-uniform), FP64; step = one proposal + commit "
-                         "of every instance, one group launch per walker-tile size, eager")
+                         f"N_det 1e2..2e5 log-uniform), {precision}; step = one proposal + "
+                         "commit of every instance, one group launch per walker-tile size, eager")
 
 
 def synth_mod():
@@ -382,7 +382,7 @@ def main():
                     help="back-to-back determinant-kernel launches per HIP event pair")
     ap.add_argument("--rows", default="",
                     help="also measure these other rows of the path (comma list of "
-                         "adjoint, uneven); reported under 'rows'")
+                         "adjoint, uneven, uneven_mixed); reported under 'rows'")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the forms, run a plain device copy (torch.neg, out=) of this many "
                          "MiB three times: the known-size reference for the HBM byte counters")
@@ -414,6 +414,8 @@ def main():
             rows[r] = run_adjoint(args.steps, args.warmup, cpu=not args.no_cpu)
         elif r == "uneven":
             rows[r] = run_uneven(min(args.steps, 10), args.warmup)
+        elif r == "uneven_mixed":
+            rows[r] = run_uneven(min(args.steps, 10), args.warmup, precision="mixed")
         else:
             raise SystemExit(f"unknown row {r!r}")
         log(f"{r}: {rows[r]['ms_per_step']:.3f} ms/step  {rows[r]['value']:.3e} walker.det/s")
