@@ -116,13 +116,18 @@ def test_adjoint_deterministic():
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("by_tile", [False, True])
-def test_group_matches_oracle_and_single_contexts(by_tile):
+@pytest.mark.parametrize("by_tile, precision", [(False, "fp64"), (True, "fp64"), (True, "mixed")])
+def test_group_matches_oracle_and_single_contexts(by_tile, precision):
+    """Groups (one launch for all instances, or one per walker-tile size)
+    equal each instance run alone with the same plan, bit for bit, and the
+    oracle: FP64 within 1e-10, the mixed form within its FP32-table gate
+    (1e-4)."""
     from paper_1106_2456_amd import Group
     wls = [synth.water_like(2, W=40, n_det=600, n_moves=6),
            synth.tiny_system(21, 3, 3, 9, 150, W=33, n_moves=6),
            synth.molecular(3, W=5, n_det=300, n_moves=6, n=12, m=40, nb=64, n_nuc=6, box=6.0)]
-    ctxs = [make_ctx(w, bind=False) for w in wls]
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    ctxs = [make_ctx(w, precision=precision, bind=False) for w in wls]
     Ws = [w.walkers.W for w in wls]
     if by_tile:
         groups = Group.by_tile(ctxs, Ws)
@@ -131,7 +136,7 @@ def test_group_matches_oracle_and_single_contexts(by_tile):
     plans = [c.get_plan(0) for c in ctxs]
     say("group plans", plans)
     # twins with the same plan, run one at a time
-    twins = [make_ctx(w, bind=False) for w in wls]
+    twins = [make_ctx(w, precision=precision, bind=False) for w in wls]
     for t, c, w in zip(twins, ctxs, wls):
         for sp in (0, 1):
             p = c.get_plan(sp)
@@ -166,7 +171,7 @@ def test_group_matches_oracle_and_single_contexts(by_tile):
             er = scaled_err(outs[i][0].cpu().numpy(), ref["ratio"], ref["scale_ratio"]).max()
             eg = scaled_err(outs[i][1].cpu().numpy(), ref["grad"], ref["scale_grad"]).max()
             el = scaled_err(outs[i][2].cpu().numpy(), ref["lap"], ref["scale_lap"]).max()
-            assert er <= 1e-10 and eg <= 1e-10 and el <= 1e-10, (k, i, er, eg, el)
+            assert er <= tol and eg <= tol and el <= tol, (k, i, er, eg, el)
             acc = w.moves.accept_half[k].astype(bool)
             p[acc, es[i]] = new_r[acc]
 
