@@ -205,8 +205,11 @@ mde_status mde_backward(mde_ctx *ctx, const double *go, double *grad_coef,
 
 /* Work decomposition of the determinant kernel for one spin: walker tile
  * (1..64, power of two), excitations per work item, threads per block
- * (64..1024).  0 keeps the current value.  Takes effect at the next
- * mde_init / mde_refresh (call mde_refresh after changing it). */
+ * (64..1024).  0 keeps the current value.  Before mde_bind_workspace the
+ * plan is kept for the bind; on a bound context it takes effect at once and
+ * the walkers' state must be set again with mde_init (MDE_STATE until
+ * then).  A group holding the context rebuilds its work items at its next
+ * call (outside a capture). */
 mde_status mde_set_plan(mde_ctx *ctx, int32_t spin, int32_t walker_tile,
                         int32_t item_exc, int32_t threads);
 mde_status mde_get_plan(const mde_ctx *ctx, int32_t spin, int32_t *walker_tile,

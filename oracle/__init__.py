@@ -191,11 +191,18 @@ def move(sysm, pos: np.ndarray, e: int, new_r: np.ndarray, coef=None):
                 scale_ratio=sc_ratio, scale_grad=sc_d[:, :3], scale_lap=sc_d[:, 3])
 
 
-def grad_lap(sysm, pos: np.ndarray, e: int, coef=None):
-    """grad_e ln Psi and lap_e Psi / Psi at R (no move)."""
+def grad_lap(sysm, pos: np.ndarray, e: int, coef=None, scales: bool = False):
+    """grad_e ln Psi and lap_e Psi / Psi at R (no move).  With ``scales`` also
+    their condition-aware scales (as in ``move``)."""
     ou, od = walker_orbitals(sysm, pos)
     r = mds(sysm, ou, od, e_deriv=e, coef=coef)
-    return r["dpsi"][:, :3] / r["psi"][:, None], r["dpsi"][:, 3] / r["psi"]
+    g = r["dpsi"][:, :3] / r["psi"][:, None]
+    lap = r["dpsi"][:, 3] / r["psi"]
+    if not scales:
+        return g, lap
+    sc = (r["dpsi_abs"] + np.abs(r["dpsi"] / r["psi"][:, None]) * r["psi_abs"][:, None]) \
+        / np.abs(r["psi"])[:, None]
+    return g, lap, sc[:, :3], sc[:, 3]
 
 
 # ---------------------------------------------------------------------------

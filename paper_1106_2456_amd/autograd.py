@@ -21,6 +21,7 @@ class MultiDetLogPsi(torch.autograd.Function):
         T_dn = T_dn.contiguous()
         la, sg, st = mctx.eval_tables(T_up, T_dn, coef)
         fctx.mctx = mctx
+        fctx.state_seq = mctx.state_seq
         fctx.save_for_backward(coef, T_up, T_dn)
         fctx.mark_non_differentiable(sg)
         return la, sg
@@ -29,9 +30,10 @@ class MultiDetLogPsi(torch.autograd.Function):
     def backward(fctx, go, gsign):
         mctx = fctx.mctx
         coef, T_up, T_dn = fctx.saved_tensors
-        # the context holds the state of its last forward; re-run it if the
-        # context was used in between (cheap relative to the backward)
-        if mctx._keep_tables[0] is not T_up or mctx._keep_tables[1] is not T_dn:
+        # the context holds the state of its last call; unless that call was
+        # this forward, evaluate this forward's tables and coefficients again
+        # (cheap relative to the backward)
+        if mctx.state_seq != fctx.state_seq:
             mctx.eval_tables(T_up, T_dn, coef)
         gc, gu, gd = mctx.backward(go.contiguous().to(torch.float64),
                                    want_coef=fctx.needs_input_grad[1],

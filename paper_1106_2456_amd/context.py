@@ -95,6 +95,10 @@ class Context:
         self._keep = []
         self.W = None
         self.workspace = None
+        # bumped by every call that changes the library-side state, so that
+        # a caller holding on to one state (the autograd Function between
+        # its forward and backward) can tell whether it is still current
+        self.state_seq = 0
 
     # -- plumbing ----------------------------------------------------------
     def _chk(self, rc, what):
@@ -156,6 +160,7 @@ class Context:
         _check_dev(orb_dn, torch.float64, (W, self.n_elec[1], 5, self.n_orb[1]), "orb_dn")
         la, sg = self._empty(W), self._empty(W)
         st = status if status is not None else torch.zeros(W, dtype=torch.int32, device=self.device)
+        self.state_seq += 1
         self._chk(lib().mde_init(self._h, _ptr(orb_up), _ptr(orb_dn), _ptr(la), _ptr(sg), _ptr(st)),
                   "init")
         return la, sg, st
@@ -164,6 +169,7 @@ class Context:
         W = self.W
         la, sg = self._empty(W), self._empty(W)
         st = status if status is not None else torch.zeros(W, dtype=torch.int32, device=self.device)
+        self.state_seq += 1
         self._chk(lib().mde_refresh(self._h, _ptr(la), _ptr(sg), _ptr(st)), "refresh")
         return la, sg, st
 
@@ -179,6 +185,7 @@ class Context:
             out = (self._empty(W), self._empty((W, 3)), self._empty(W),
                    torch.zeros(W, dtype=torch.int32, device=self.device))
         r, g, l, st = out
+        self.state_seq += 1
         self._chk(lib().mde_propose(self._h, e, _ptr(new_orb), _ptr(r), _ptr(g), _ptr(l), _ptr(st)),
                   "propose")
         return out
@@ -191,12 +198,14 @@ class Context:
             out = (self._empty((W, 3)), self._empty(W),
                    torch.zeros(W, dtype=torch.int32, device=self.device))
         g, l, st = out
+        self.state_seq += 1
         self._chk(lib().mde_grad_lap(self._h, e, _ptr(cur_orb), _ptr(g), _ptr(l), _ptr(st)),
                   "grad_lap")
         return out
 
     def accept(self, e: int, mask: torch.Tensor):
         _check_dev(mask, torch.uint8, (self.W,), "accept mask")
+        self.state_seq += 1
         self._chk(lib().mde_accept(self._h, e, _ptr(mask)), "accept")
 
     def export(self, what: str, spin: int = 0) -> torch.Tensor:
@@ -220,7 +229,7 @@ class Context:
         _check_dev(coef, torch.float64, (self.n_det,), "coef")
         la, sg = self._empty(W), self._empty(W)
         st = torch.zeros(W, dtype=torch.int32, device=self.device)
-        self._keep_tables = (T_up, T_dn)
+        self.state_seq += 1
         self._chk(lib().mde_eval_tables(self._h, _ptr(T_up), _ptr(T_dn), _ptr(coef), _ptr(la),
                                         _ptr(sg), _ptr(st)), "eval_tables")
         return la, sg, st

@@ -653,7 +653,7 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
                                                  unsigned char *tab_raw, const double (&acc)[NSUM],
                                                  int tid, int nthr) {
     constexpr int WT = 64, WTP = lds_row_stride(64);
-    const int n = S.n, m = S.m, no = S.no, W = I.W, nm = n * m;
+    const int n = S.n, m = S.m, no = S.no, W = I.W;
     const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
     const int w0 = it.tile * WT;
     const auto orb = MDE_G(double, mv.new_orb);

@@ -1101,6 +1101,31 @@ hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int32_t v, size_t n) {
     return hipGetLastError();
 }
 
+// per-instance move arguments written from kernel arguments, MOVE_BATCH at
+// a time (a launch's arguments are copied by value, also into graphs)
+constexpr int MOVE_BATCH = 24;
+struct MoveBatch {
+    MoveArgs m[MOVE_BATCH];
+};
+static_assert(sizeof(MoveBatch) <= 3072, "kernel argument block");
+
+__global__ void k_set_moves(MoveArgs *__restrict__ dst, MoveBatch b, int n) {
+    const int i = threadIdx.x;
+    if (i < n) dst[i] = b.m[i];
+}
+
+hipError_t launch_set_moves(hipStream_t st, MoveArgs *d_moves, const MoveArgs *h_moves, int n) {
+    for (int off = 0; off < n; off += MOVE_BATCH) {
+        MoveBatch b{};
+        const int cnt = n - off < MOVE_BATCH ? n - off : MOVE_BATCH;
+        for (int i = 0; i < cnt; ++i) b.m[i] = h_moves[off + i];
+        hipLaunchKernelGGL(k_set_moves, dim3(1), dim3(64), 0, st, d_moves + off, b, cnt);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_reset_counter(hipStream_t st, int32_t *counter) {
     return launch_fill_i32(st, counter, 0, 16);
 }

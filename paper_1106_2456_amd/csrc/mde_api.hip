@@ -66,7 +66,6 @@ struct Plan {
 struct mde_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<void *> host_bufs;
 };
 
 struct mde_ctx {
@@ -118,6 +117,9 @@ struct mde_ctx {
     bool prof_on = false;
     // plan fields chosen by the caller (kept when the default plan is applied)
     bool user_wt = false, user_thr[2] = {false, false}, user_item[2] = {false, false};
+    // bumped whenever the work layout is re-established (apply_plan): a group
+    // built over this context holds the generation it copied
+    long plan_gen = 0;
 };
 
 // default plan for W walkers, keeping the fields the caller set
@@ -137,14 +139,8 @@ struct mde_group {
     int n_items = 0;
     ItemQueues queues{};
     std::vector<MoveArgs> hmoves;
-    // pinned upload ring
-    static constexpr int RING = 64;
-    MoveArgs *pinned = nullptr;
-    hipEvent_t ev[RING] = {};
-    bool ev_used[RING] = {};
-    int ring_pos = 0;
+    std::vector<long> plan_gen;   // each member's plan generation at the last rebuild
     bool capturing = false;
-    std::vector<void *> capture_bufs;
     std::string err;
 };
 
@@ -786,6 +782,7 @@ static mde_status apply_plan(mde_ctx *c) {
     MDE_HIP(c, hipMemcpy(c->d_inst, &c->h, sizeof(InstDev), hipMemcpyHostToDevice));
     c->R_valid[0] = c->R_valid[1] = false;
     c->C_valid[0] = c->C_valid[1] = false;
+    c->plan_gen++;
     return MDE_OK;
 }
 
@@ -1683,7 +1680,6 @@ mde_status mde_graph_destroy(mde_graph *g) {
     if (!g) return MDE_OK;
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    for (void *p : g->host_bufs) (void)hipHostFree(p);
     delete g;
     return MDE_OK;
 }
@@ -1791,6 +1787,8 @@ static mde_status group_rebuild(mde_group *g) {
     int per_cu = (int)std::min<size_t>(160 * 1024 / lds, 2048 / g->threads);
     per_cu = std::max(per_cu, 1);
     g->grid = std::max(1, (int)std::min<size_t>(sorted.size(), (size_t)g->ctx[0]->n_cu * per_cu));
+    g->plan_gen.resize(n);
+    for (int i = 0; i < n; ++i) g->plan_gen[i] = g->ctx[i]->plan_gen;
     return MDE_OK;
 }
 
@@ -1833,15 +1831,6 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
     }
     g->d_items = cv.take<WorkItem>(max_items);
     g->d_bounds = cv.take<int32_t>(max_items * 2 * (1024 / 64));
-    if (hipHostMalloc((void **)&g->pinned, sizeof(MoveArgs) * n * mde_group::RING) != hipSuccess) {
-        delete g;
-        return MDE_NOMEM;
-    }
-    for (int r = 0; r < mde_group::RING; ++r)
-        if (hipEventCreateWithFlags(&g->ev[r], hipEventDisableTiming) != hipSuccess) {
-            delete g;
-            return MDE_DEVICE;
-        }
     g->hmoves.assign(n, MoveArgs{});
     mde_status st = group_rebuild(g);
     if (st) {
@@ -1854,42 +1843,37 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
 
 mde_status mde_group_destroy(mde_group *g) {
     if (!g) return MDE_OK;
-    for (int r = 0; r < mde_group::RING; ++r)
-        if (g->ev[r]) (void)hipEventDestroy(g->ev[r]);
-    if (g->pinned) (void)hipHostFree(g->pinned);
-    for (void *p : g->capture_bufs) (void)hipHostFree(p);
     delete g;
     return MDE_OK;
 }
 
-// copy the per-instance move arguments to the device (stream-ordered)
+// Write the per-instance move arguments to the device array the kernels
+// read, stream-ordered, as arguments of small copy kernels: nothing is read
+// from host memory when the copy runs, so a captured graph carries the
+// arguments of the captured call by value and the call allocates nothing.
 static mde_status group_upload(mde_group *g) {
     const int n = (int)g->ctx.size();
-    MoveArgs *src = nullptr;
-    if (g->capturing) {
-        // a captured copy reads its host buffer at every replay: keep one per call
-        if (hipHostMalloc((void **)&src, sizeof(MoveArgs) * n) != hipSuccess)
-            MDE_GFAIL(g, MDE_NOMEM, "pinned buffer for capture");
-        g->capture_bufs.push_back(src);
-    } else {
-        const int r = g->ring_pos;
-        g->ring_pos = (g->ring_pos + 1) % mde_group::RING;
-        if (g->ev_used[r] && hipEventSynchronize(g->ev[r]) != hipSuccess)
-            MDE_GFAIL(g, MDE_DEVICE, "event wait");
-        src = g->pinned + (size_t)r * n;
-        std::memcpy(src, g->hmoves.data(), sizeof(MoveArgs) * n);
-        if (hipMemcpyAsync(g->d_moves, src, sizeof(MoveArgs) * n, hipMemcpyHostToDevice, g->stream) !=
-            hipSuccess)
-            MDE_GFAIL(g, MDE_DEVICE, "argument upload");
-        if (hipEventRecord(g->ev[r], g->stream) != hipSuccess) MDE_GFAIL(g, MDE_DEVICE, "event record");
-        g->ev_used[r] = true;
-        return MDE_OK;
-    }
-    std::memcpy(src, g->hmoves.data(), sizeof(MoveArgs) * n);
-    if (hipMemcpyAsync(g->d_moves, src, sizeof(MoveArgs) * n, hipMemcpyHostToDevice, g->stream) !=
-        hipSuccess)
+    if (launch_set_moves(g->stream, g->d_moves, g->hmoves.data(), n) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "argument upload");
     return MDE_OK;
+}
+
+// A member whose plan changed since the group copied its work items (a
+// mde_set_plan + refresh or mde_autotune) has a new table layout: rebuild
+// the group's items from it, outside a capture; members must still share
+// one walker tile.
+static mde_status group_check_plans(mde_group *g) {
+    bool stale = false;
+    for (size_t i = 0; i < g->ctx.size(); ++i) stale |= g->ctx[i]->plan_gen != g->plan_gen[i];
+    if (!stale) return MDE_OK;
+    if (g->capturing)
+        MDE_GFAIL(g, MDE_STATE, "a member's plan changed since the group was built; "
+                                "call the group outside a capture first");
+    for (size_t i = 0; i < g->ctx.size(); ++i)
+        if (g->ctx[i]->WT != g->WT)
+            MDE_GFAIL(g, MDE_STATE, "instance %zu changed its walker tile (%d, group %d)", i,
+                      g->ctx[i]->WT, g->WT);
+    return group_rebuild(g);
 }
 
 mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const *new_orb,
@@ -1897,6 +1881,10 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const
                              int32_t *const *status) {
     if (!g || !e || !new_orb) return MDE_INVALID;
     const int n = (int)g->ctx.size();
+    {
+        mde_status pst = group_check_plans(g);
+        if (pst) return pst;
+    }
     for (int i = 0; i < n; ++i) {
         mde_ctx *c = g->ctx[i];
         if (!c->initialized || c->adjoint_state) MDE_GFAIL(g, MDE_STATE, "instance %d not initialised", i);
@@ -1942,6 +1930,10 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const
 mde_status mde_group_accept(mde_group *g, const int32_t *e, const uint8_t *const *accept) {
     if (!g || !e || !accept) return MDE_INVALID;
     const int n = (int)g->ctx.size();
+    {
+        mde_status pst = group_check_plans(g);
+        if (pst) return pst;
+    }
     for (int i = 0; i < n; ++i) {
         mde_ctx *c = g->ctx[i];
         if (c->pending_e != e[i]) MDE_GFAIL(g, MDE_STATE, "instance %d: no pending proposal", i);
@@ -2004,7 +1996,6 @@ mde_status mde_group_capture_end(mde_group *g, mde_graph **out) {
         delete gr;
         MDE_GFAIL(g, MDE_DEVICE, "instantiate");
     }
-    gr->host_bufs.swap(g->capture_bufs);
     *out = gr;
     return MDE_OK;
 }

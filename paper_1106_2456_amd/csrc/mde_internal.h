@@ -242,6 +242,9 @@ hipError_t launch_sgauss(hipStream_t st, int nb, const double *centres, const do
                          int n_orb, const double *mo, int npos, const double *pos,
                          double *out);
 hipError_t launch_reset_counter(hipStream_t st, int32_t *counter);
+// copy n per-instance move arguments (host array) to d_moves, as kernel
+// arguments (no host buffer is read when the copy runs)
+hipError_t launch_set_moves(hipStream_t st, MoveArgs *d_moves, const MoveArgs *h_moves, int n);
 hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int32_t v, size_t n);
 
 }  // namespace mde

@@ -73,3 +73,43 @@ def test_two_routes_agree():
         su, lu = np.linalg.slogdet(ou[w, :, 0, :5])
         sd, ld = np.linalg.slogdet(od[w, :, 0, :5])
         assert abs(out2[1] - (lu + ld + l[w])) < 1e-10 * abs(out2[1])
+
+
+def test_singular_excited_table_matrix():
+    """The table route's fallback for a singular excited matrix X_u (its
+    cofactors by column replacement): a double excitation whose two table
+    columns are exactly proportional has det X_u = 0, yet contributes
+    cofactors to dlog|N|/dT.  Checked against central differences of the
+    oracle's own forward, which takes no such branch."""
+    ex_u = synth.Excitations(np.array([0, 0, 1, 3, 4], np.int32),
+                             np.array([2, 0, 1, 1], np.int32),
+                             np.array([5, 3, 4, 6], np.int32))
+    ex_d = synth.Excitations(np.array([0, 0, 1], np.int32),
+                             np.array([1], np.int32), np.array([3], np.int32))
+    det_up = np.array([0, 1, 2, 0, 2, 3], np.int32)
+    det_dn = np.array([0, 0, 0, 1, 1, 1], np.int32)
+    coef = np.array([1.0, 0.4, -0.7, 0.3, 0.25, -0.5])
+    ex = synth.Excitations(np.zeros(2, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    sysm = synth.System((3, 2), (7, 5), np.zeros((1, 3)), np.zeros((1, 3)), np.ones(1),
+                        np.zeros((7, 1)), (ex_u, ex_d), coef, det_up, det_dn)
+    # dyadic entries: the double (0,1 -> 3,4) reads columns 0 and 1 of T_up,
+    # and column 1 = 1.5 x column 0 exactly, so X_u is singular in floating point
+    Tu = np.array([[[0.5, 0.75, -0.25, 1.0],
+                    [-1.0, -1.5, 0.5, 0.25],
+                    [0.25, 0.375, 2.0, -0.5]]])
+    Td = np.array([[[0.5, -0.25, 1.5], [1.25, 0.75, -1.0]]])
+    s, l, gc, gu, gd = oracle.tables(sysm, Tu, Td)
+    assert s[0] != 0.0
+    # the double's ratio is exactly zero
+    assert gc[0, 2] == 0.0
+    h = 1e-6
+    for r in range(3):
+        for p in range(4):
+            Tp, Tm = Tu.copy(), Tu.copy()
+            Tp[0, r, p] += h
+            Tm[0, r, p] -= h
+            fd = (oracle.tables(sysm, Tp, Td)[1] - oracle.tables(sysm, Tm, Td)[1]) / (2 * h)
+            assert abs(fd[0] - gu[0, r, p]) <= 1e-8 * (1 + abs(fd[0])), (r, p, fd, gu[0, r, p])
+    # the cofactors reached through the fallback are not zero: the singular
+    # double is the only determinant holding hole 1 with particle 4
+    assert abs(gu[0, 1, 1]) > 1e-3
