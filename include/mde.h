@@ -65,11 +65,16 @@ typedef enum {
                              Sherman-Morrison table update, the small
                              determinants, LU, denominators and CI sums are
                              computed in FP64                                 */
-    MDE_MIXED_GEMM = 2    /* as MDE_MIXED, but every proposal rebuilds the
+    MDE_MIXED_GEMM = 2,   /* as MDE_MIXED, but every proposal rebuilds the
                              table with one FP32 MFMA GEMM T' = A'^-1 Phi'_V
                              (Algorithm 1 step 3) instead of the rank-one
-                             update; its error grows with the condition
-                             number of the reference matrix                 */
+                             update, FP32 operands and FP32 accumulation over
+                             all of K = n; its error scales with
+                             |A'^-1| |Phi'_V| rather than |T'|              */
+    MDE_MIXED_GEMM_KSUM64 = 3  /* as MDE_MIXED_GEMM, but each MFMA forms one
+                             K-block of 4 in FP32 and the K-blocks are summed
+                             in FP64 (an alternative with a smaller GEMM
+                             error at the same operand precision)           */
 } mde_precision;
 
 /* per-walker status bits */

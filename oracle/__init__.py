@@ -56,6 +56,8 @@ def lib():
                                          [C.c_int64, _dp, _ip, _ip, _dp, _dp, _dp, _dp])
         L.oracle_tables_batch.argtypes = ([C.c_int] * 5 + [_dp, _dp] + exc + exc +
                                           [C.c_int64, _dp, _ip, _ip, _dp, _dp, _dp, _dp])
+        L.oracle_mixed_scales_batch.argtypes = ([C.c_int] * 5 + [_dp, _dp, C.c_int, _dp] + exc + exc +
+                                                [C.c_int64, _dp, _ip, _ip, _dp, _dp])
         L.oracle_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -249,3 +251,37 @@ def tables(sysm, T_up: np.ndarray, T_dn: np.ndarray, coef=None):
     if rc != 0:
         raise RuntimeError("oracle_tables_batch failed")
     return out2[:, 0], out2[:, 1], gc, gu, gd
+
+
+# ---------------------------------------------------------------------------
+# error scales of the FP32-table forms
+# ---------------------------------------------------------------------------
+
+def mixed_scales(sysm, pos: np.ndarray, e: int, new_r: np.ndarray, coef=None):
+    """First-order error scales of one proposed move (as ``move``) for forms
+    that keep table entries in FP32.  A relative perturbation eps of every
+    FP32-stored entry moves each output x by at most eps * X to first order.
+
+    Returns ``round`` [W, 5] (entries rounded to FP32: E = |entry|),
+    ``gemm`` [W, 5] (entries formed by an FP32 product of A^-1 and Phi_V:
+    E = |A^-1| |Phi_V|), columns (ratio, d/dx, d/dy, d/dz, laplacian), and
+    ``vals`` [W, 5], the same outputs computed through the tables (pinned
+    against ``move``)."""
+    pos = _f64(pos)
+    W = pos.shape[0]
+    nu, nd = sysm.n_elec
+    nou, nod = sysm.n_orb
+    ou, od = walker_orbitals(sysm, pos)
+    spin = 0 if e < nu else 1
+    blk = _f64(orbitals(sysm, spin, _f64(new_r)))
+    ex_u, ex_d = sysm.exc
+    coef = _f64(sysm.coef if coef is None else coef)
+    out = np.empty((W, 2, 5))
+    vals = np.empty((W, 5))
+    rc = lib().oracle_mixed_scales_batch(W, nu, nd, nou, nod, ou, od, int(e), blk,
+                                         *_exc_args(ex_u), *_exc_args(ex_d),
+                                         int(coef.shape[0]), coef, _i32(sysm.det_up),
+                                         _i32(sysm.det_dn), out, vals)
+    if rc != 0:
+        raise RuntimeError("oracle_mixed_scales_batch failed (singular reference?)")
+    return dict(round=out[:, 0].copy(), gemm=out[:, 1].copy(), vals=vals)

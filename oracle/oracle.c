@@ -28,6 +28,10 @@
  * Orbitals: unnormalised s-Gaussians chi_b(r) = exp(-a_b |r - R_b|^2) and
  * molecular orbitals phi_p = sum_b mo[p][b] chi_b, with the closed forms
  *   grad chi = -2 a (r - R) chi,   lap chi = (4 a^2 |r - R|^2 - 6 a) chi.
+ *
+ * One function at the end (oracle_mixed_scales_batch) is a measuring tool
+ * rather than a definition: it forms the tables of Sec. III explicitly to
+ * bound how far FP32 storage of their entries can move each output.
  */
 #include <math.h>
 #include <stdint.h>
@@ -485,6 +489,275 @@ int oracle_tables_batch(int W, int n_up, int n_dn, int m_up, int m_dn,
                              n_det, coef, iu, id, out2 + 2 * (size_t)w,
                              grad_c + (size_t)w * n_det,
                              gT_up + w * su, gT_dn + w * sd);
+    return err ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* first-order error scales of the forms that keep tables in FP32           */
+/* (a measuring tool for the parity tests, not part of the values above)    */
+/* ------------------------------------------------------------------------ */
+/*
+ * Table T = A^-1 Phi (Sec. III, table definition); an excitation's ratio is
+ * det S with S[j][l] = T[h_j][p_l] (Sec. III read-off).  If every entry is
+ * perturbed by |dS_jl| <= eps E_jl, det S moves by at most
+ *     eps P_E(S),   P_E(S) = sum_jl E_jl |cof(S)_jl|,   cof = d det S / d S_jl
+ * to first order.  E = |S| for entries stored in FP32 (rounding), and
+ * E = (|A^-1| |Phi_V|)[h_j][p_l] for entries formed by an FP32 product of
+ * A^-1 and Phi_V (a matrix product's error is bounded entrywise by a
+ * multiple of the product of the absolute values).
+ *
+ * Derivatives of the moved electron i at R' (Sec. IV-A): with c' = A'^-1 e_i,
+ * rho^a = d^a_O . c' and g^a = d^a_V - d^a_O^T T' (d^a = grad^a of the new
+ * orbital row), grad^a D_u(R') / D_0(R') is the bordered determinant
+ *     det [[rho^a, -g^a[p]^T], [c'[h], S'_u]]
+ * (row replacement read through the determinant lemma); its entries other
+ * than rho^a carry FP32 storage in those forms: E = |g^a| or
+ * |d^a_V| + |d^a_O^T A'^-1| |Phi'_V| (product form), |c'|, and E of S'.
+ *
+ * For x = sum_I a_I / sum_I b_I with a_I, b_I products of the two spins'
+ * determinants (ratio = rho N'/N, grad^a = A^a / N'), first order gives
+ * |dx| <= eps X with
+ *   Q(N)  = sum_I |c_I| (P(S_up,I) |R_dn,I| + |R_up,I| P(S_dn,I))
+ *   ratio: X = |x| (Q(N')/|N'| + Q(N)/|N|)
+ *   grad^a: X = (Q(A^a) + |x| Q(N')) / |N'|
+ * out[w][kind][5] = X for (ratio, d/dx, d/dy, d/dz, laplacian), kind 0:
+ * rounding of the entries, kind 1: product-formed entries.  vals[w][5] = the
+ * same outputs computed by this table route (pinned against the full-LU
+ * route of oracle_mds_batch).
+ */
+
+/* det and cofactor matrix of a k x k matrix (row-major) by LU of each minor */
+static double det_cof(int k, const double *M, double *cof)
+{
+    double a[81], s1, l1;
+    int perm[9];
+    if (k == 1) { cof[0] = 1.0; return M[0]; }
+    for (int j = 0; j < k; ++j)
+        for (int l = 0; l < k; ++l) {
+            int r = 0;
+            for (int jj = 0; jj < k; ++jj) {
+                if (jj == j) continue;
+                int c = 0;
+                for (int ll = 0; ll < k; ++ll) {
+                    if (ll == l) continue;
+                    a[r * (k - 1) + c] = M[jj * k + ll];
+                    ++c;
+                }
+                ++r;
+            }
+            lu_factor(k - 1, a, perm, &s1, &l1);
+            cof[j * k + l] = (((j + l) & 1) ? -1.0 : 1.0) * s1 * exp(l1);
+        }
+    double d = 0.0;
+    for (int l = 0; l < k; ++l) d += M[l] * cof[l];
+    return d;
+}
+
+/* inverse, table and product scale of one spin: phi [n][no] values */
+static int spin_tables(int n, int no, const double *phi, double *B, double *T, double *E,
+                       double *sign, double *logabs)
+{
+    double A[OR_MAXN * OR_MAXN];
+    int perm[OR_MAXN];
+    const int m = no - n;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[i * n + j] = phi[(size_t)i * no + j];
+    lu_factor(n, A, perm, sign, logabs);
+    if (*sign == 0.0) return 1;
+    lu_inverse(n, A, perm, B);
+    for (int r = 0; r < n; ++r)
+        for (int p = 0; p < m; ++p) {
+            double t = 0.0, e = 0.0;
+            for (int k = 0; k < n; ++k) {
+                t += B[r * n + k] * phi[(size_t)k * no + n + p];
+                e += fabs(B[r * n + k]) * fabs(phi[(size_t)k * no + n + p]);
+            }
+            T[(size_t)r * m + p] = t;
+            E[(size_t)r * m + p] = e;
+        }
+    return 0;
+}
+
+/* ratio, P and P_E of every excitation of one spin from its table */
+static void spin_ratios(int n, int m, const double *T, const double *E, int nx, const int *off,
+                        const int *hs, const int *ps, double *R, double *P, double *PE)
+{
+    double S[81], cof[81];
+    for (int u = 0; u < nx; ++u) {
+        const int k = off[u + 1] - off[u];
+        if (k == 0) { R[u] = 1.0; P[u] = 0.0; PE[u] = 0.0; continue; }
+        const int *h = hs + off[u], *p = ps + off[u];
+        for (int j = 0; j < k; ++j)
+            for (int l = 0; l < k; ++l) S[j * k + l] = T[(size_t)h[j] * m + p[l] - n];
+        R[u] = det_cof(k, S, cof);
+        double a = 0.0, b = 0.0;
+        for (int j = 0; j < k; ++j)
+            for (int l = 0; l < k; ++l) {
+                a += fabs(S[j * k + l]) * fabs(cof[j * k + l]);
+                b += E[(size_t)h[j] * m + p[l] - n] * fabs(cof[j * k + l]);
+            }
+        P[u] = a;
+        PE[u] = b;
+    }
+}
+
+static int mixed_walker(int n_up, int n_dn, int no_up, int no_dn, const double *orb_up,
+                        const double *orb_dn, int e, const double *blk,
+                        int nx_up, const int *off_up, const int *h_up, const int *p_up,
+                        int nx_dn, const int *off_dn, const int *h_dn, const int *p_dn,
+                        int64_t n_det, const double *coef, const int *iu, const int *id,
+                        double *out, double *vals)
+{
+    const int ms = e < n_up ? 0 : 1, os = 1 - ms;
+    const int n_s[2] = {n_up, n_dn}, no_s[2] = {no_up, no_dn}, nx[2] = {nx_up, nx_dn};
+    const double *orb_s[2] = {orb_up, orb_dn};
+    const int *off_s[2] = {off_up, off_dn}, *h_s[2] = {h_up, h_dn}, *p_s[2] = {p_up, p_dn};
+    const int n = n_s[ms], no = no_s[ms], m = no - n, row = ms == 0 ? e : e - n_up;
+    const int no2 = no_s[os], n2 = n_s[os], m2 = no2 - n2;
+    for (int q = 0; q < 10; ++q) out[q] = NAN;
+    for (int q = 0; q < 5; ++q) vals[q] = NAN;
+    int nmax = n > n2 ? n : n2, mmax = m > m2 ? m : m2;
+    double *phi = malloc(sizeof(double) * (size_t)nmax * (nmax + mmax));
+    double *phi2 = malloc(sizeof(double) * (size_t)nmax * (nmax + mmax));
+    double *B = malloc(sizeof(double) * (size_t)nmax * nmax);
+    double *Bp = malloc(sizeof(double) * (size_t)nmax * nmax);
+    double *T = malloc(sizeof(double) * (size_t)nmax * mmax), *E = malloc(sizeof(double) * (size_t)nmax * mmax);
+    double *Tp = malloc(sizeof(double) * (size_t)nmax * mmax), *Ep = malloc(sizeof(double) * (size_t)nmax * mmax);
+    double *To = malloc(sizeof(double) * (size_t)nmax * mmax), *Eo = malloc(sizeof(double) * (size_t)nmax * mmax);
+    double *R = malloc(sizeof(double) * nx[ms] * 3), *Rp = malloc(sizeof(double) * nx[ms] * 3);
+    double *Ro = malloc(sizeof(double) * nx[os] * 3);
+    double *G = malloc(sizeof(double) * nx[ms] * 12);
+    int rc = 0;
+    /* moving spin at R and at R' (row `row` replaced), other spin at R */
+    for (int i = 0; i < n; ++i)
+        for (int p = 0; p < no; ++p) {
+            phi[(size_t)i * no + p] = orb_s[ms][((size_t)i * 5) * no + p];
+            phi2[(size_t)i * no + p] = i == row ? blk[p] : phi[(size_t)i * no + p];
+        }
+    double s0, l0, s1, l1, so, lo;
+    rc |= spin_tables(n, no, phi, B, T, E, &s0, &l0);
+    rc |= spin_tables(n, no, phi2, Bp, Tp, Ep, &s1, &l1);
+    {
+        double *ph = malloc(sizeof(double) * (size_t)n2 * no2);
+        for (int i = 0; i < n2; ++i)
+            for (int p = 0; p < no2; ++p) ph[(size_t)i * no2 + p] = orb_s[os][((size_t)i * 5) * no2 + p];
+        rc |= spin_tables(n2, no2, ph, B, To, Eo, &so, &lo);   /* B reused as scratch */
+        free(ph);
+        /* restore B of the moving spin at R (not needed further) */
+    }
+    if (rc == 0) {
+        spin_ratios(n, m, T, E, nx[ms], off_s[ms], h_s[ms], p_s[ms], R, R + nx[ms], R + 2 * nx[ms]);
+        spin_ratios(n, m, Tp, Ep, nx[ms], off_s[ms], h_s[ms], p_s[ms], Rp, Rp + nx[ms], Rp + 2 * nx[ms]);
+        spin_ratios(n2, m2, To, Eo, nx[os], off_s[os], h_s[os], p_s[os], Ro, Ro + nx[os], Ro + 2 * nx[os]);
+        /* derivative factors at R' */
+        double cp[OR_MAXN], rho[4], g[4][256], Eg[4][256];
+        for (int r = 0; r < n; ++r) cp[r] = Bp[r * n + row];
+        for (int a = 0; a < 4; ++a) {
+            const double *d = blk + (size_t)(1 + a) * no;
+            double ra = 0.0, ea[OR_MAXN];
+            for (int r = 0; r < n; ++r) ra += d[r] * cp[r];
+            rho[a] = ra;
+            for (int j = 0; j < n; ++j) {
+                double t = 0.0;
+                for (int r = 0; r < n; ++r) t += d[r] * Bp[r * n + j];
+                ea[j] = t;
+            }
+            for (int p = 0; p < m; ++p) {
+                double t = d[n + p], ee = 0.0;
+                for (int r = 0; r < n; ++r) {
+                    t -= d[r] * Tp[(size_t)r * m + p];
+                    ee += fabs(ea[r]) * fabs(phi2[(size_t)r * no + n + p]);
+                }
+                g[a][p] = t;
+                Eg[a][p] = fabs(d[n + p]) + ee;
+            }
+        }
+        /* bordered determinants per excitation of the moving spin */
+        double Bo[100], cof[100];
+        for (int u = 0; u < nx[ms]; ++u) {
+            const int k = off_s[ms][u + 1] - off_s[ms][u];
+            const int *h = h_s[ms] + off_s[ms][u], *p = p_s[ms] + off_s[ms][u];
+            const int K = k + 1;
+            for (int a = 0; a < 4; ++a) {
+                Bo[0] = rho[a];
+                for (int l = 0; l < k; ++l) Bo[1 + l] = -g[a][p[l] - n];
+                for (int j = 0; j < k; ++j) {
+                    Bo[(1 + j) * K] = cp[h[j]];
+                    for (int l = 0; l < k; ++l) Bo[(1 + j) * K + 1 + l] = Tp[(size_t)h[j] * m + p[l] - n];
+                }
+                const double d = det_cof(K, Bo, cof);
+                double pa = 0.0, pb = 0.0;
+                for (int l = 0; l < k; ++l) {
+                    pa += fabs(Bo[1 + l]) * fabs(cof[1 + l]);
+                    pb += Eg[a][p[l] - n] * fabs(cof[1 + l]);
+                }
+                for (int j = 0; j < k; ++j) {
+                    const double cc = fabs(cp[h[j]]) * fabs(cof[(1 + j) * K]);
+                    pa += cc;
+                    pb += cc;
+                    for (int l = 0; l < k; ++l) {
+                        const double cf = fabs(cof[(1 + j) * K + 1 + l]);
+                        pa += fabs(Bo[(1 + j) * K + 1 + l]) * cf;
+                        pb += Ep[(size_t)h[j] * m + p[l] - n] * cf;
+                    }
+                }
+                G[(size_t)u * 12 + a] = d;
+                G[(size_t)u * 12 + 4 + a] = pa;
+                G[(size_t)u * 12 + 8 + a] = pb;
+            }
+        }
+        /* CI sums */
+        double N0 = 0, N1 = 0, Q0[2] = {0, 0}, Q1[2] = {0, 0}, A[4] = {0, 0, 0, 0}, QA[2][4];
+        for (int a = 0; a < 4; ++a) QA[0][a] = QA[1][a] = 0.0;
+        const int nms = nx[ms], nos = nx[os];
+        for (int64_t I = 0; I < n_det; ++I) {
+            const int um = ms == 0 ? iu[I] : id[I], uo = ms == 0 ? id[I] : iu[I];
+            const double c = coef[I], ac = fabs(c);
+            const double ro = Ro[uo], aro = fabs(ro);
+            N0 += c * R[um] * ro;
+            N1 += c * Rp[um] * ro;
+            for (int kind = 0; kind < 2; ++kind) {
+                const double po = Ro[(1 + kind) * nos + uo];
+                Q0[kind] += ac * (R[(1 + kind) * nms + um] * aro + fabs(R[um]) * po);
+                Q1[kind] += ac * (Rp[(1 + kind) * nms + um] * aro + fabs(Rp[um]) * po);
+                for (int a = 0; a < 4; ++a)
+                    QA[kind][a] += ac * (G[(size_t)um * 12 + 4 + 4 * kind + a] * aro +
+                                         fabs(G[(size_t)um * 12 + a]) * po);
+            }
+            for (int a = 0; a < 4; ++a) A[a] += c * G[(size_t)um * 12 + a] * ro;
+        }
+        const double rho0 = s0 * s1 * exp(l1 - l0);
+        const double ratio = rho0 * N1 / N0;
+        vals[0] = ratio;
+        for (int a = 0; a < 4; ++a) vals[1 + a] = A[a] / N1;
+        for (int kind = 0; kind < 2; ++kind) {
+            out[kind * 5] = fabs(ratio) * (Q1[kind] / fabs(N1) + Q0[kind] / fabs(N0));
+            for (int a = 0; a < 4; ++a)
+                out[kind * 5 + 1 + a] = (QA[kind][a] + fabs(vals[1 + a]) * Q1[kind]) / fabs(N1);
+        }
+    }
+    free(phi); free(phi2); free(B); free(Bp); free(T); free(E); free(Tp); free(Ep);
+    free(To); free(Eo); free(R); free(Rp); free(Ro); free(G);
+    return rc ? 1 : 0;
+}
+
+int oracle_mixed_scales_batch(int W, int n_up, int n_dn, int no_up, int no_dn,
+                              const double *orb_up, const double *orb_dn, int e,
+                              const double *blk,
+                              int nx_up, const int *off_up, const int *h_up, const int *p_up,
+                              int nx_dn, const int *off_dn, const int *h_dn, const int *p_dn,
+                              int64_t n_det, const double *coef, const int *iu, const int *id,
+                              double *out, double *vals)
+{
+    int err = 0;
+    const size_t su = (size_t)n_up * 5 * no_up, sd = (size_t)n_dn * 5 * no_dn;
+    const size_t sb = (size_t)5 * (e < n_up ? no_up : no_dn);
+    if (n_up > OR_MAXN || n_dn > OR_MAXN || no_up - n_up > 256 || no_dn - n_dn > 256) return -1;
+#pragma omp parallel for schedule(dynamic) reduction(|: err)
+    for (int w = 0; w < W; ++w)
+        err |= mixed_walker(n_up, n_dn, no_up, no_dn, orb_up + w * su, orb_dn + w * sd, e,
+                            blk + w * sb, nx_up, off_up, h_up, p_up, nx_dn, off_dn, h_dn, p_dn,
+                            n_det, coef, iu, id, out + (size_t)w * 10, vals + (size_t)w * 5);
     return err ? -1 : 0;
 }
 

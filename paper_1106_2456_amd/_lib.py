@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libmde.so")
 
 MDE_OK, MDE_INVALID, MDE_NOMEM, MDE_DEVICE, MDE_STATE, MDE_UNSUPPORTED = range(6)
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "STATE", 5: "UNSUPPORTED"}
-MDE_FP64, MDE_MIXED, MDE_MIXED_GEMM = 0, 1, 2
+MDE_FP64, MDE_MIXED, MDE_MIXED_GEMM, MDE_MIXED_GEMM_KSUM64 = 0, 1, 2, 3
 ST_SINGULAR_REF, ST_SMALL_RATIO, ST_NONFINITE, ST_ZERO_PSI = 1, 2, 4, 8
 
 

@@ -13,9 +13,11 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from ._lib import (MDE_FP64, MDE_MIXED, MDE_MIXED_GEMM, MdeDesc, MdeError, lib)
+from ._lib import (MDE_FP64, MDE_MIXED, MDE_MIXED_GEMM, MDE_MIXED_GEMM_KSUM64, MdeDesc, MdeError,
+                   lib)
 
-PRECISIONS = {"fp64": MDE_FP64, "mixed": MDE_MIXED, "mixed_gemm": MDE_MIXED_GEMM}
+PRECISIONS = {"fp64": MDE_FP64, "mixed": MDE_MIXED, "mixed_gemm": MDE_MIXED_GEMM,
+              "mixed_gemm_ksum64": MDE_MIXED_GEMM_KSUM64}
 
 
 def _ptr(t) -> Optional[int]:

@@ -36,10 +36,10 @@ k_lu_inverse(const InstDev *__restrict__ insts, int spin, const double *__restri
             const int i = idx / no, p = idx - i * no;
             const double v = orb_in[((size_t)(w * n + i) * 5) * no + p];
             S.Phi[(size_t)w * n * no + idx] = v;
-            if (I.prec == 2 && p >= n)
+            if (I.prec >= 2 && p >= n)
                 S.PhiV32[((size_t)w * n + i) * S.m + (p - n)] = (float)v;
         }
-    } else if (I.prec == 2) {
+    } else if (I.prec >= 2) {
         for (int idx = lane; idx < n * S.m; idx += 64) {
             const int i = idx / S.m, p = idx - i * S.m;
             S.PhiV32[(size_t)w * n * S.m + idx] = (float)S.Phi[((size_t)w * n + i) * no + n + p];
@@ -181,10 +181,10 @@ k_refresh_small(const InstDev *__restrict__ insts, int spin, const double *__res
                 const int p = p0 + u;
                 if (p >= no) break;
                 Phw[g * no + p] = v[u];
-                if (prec == 2 && p >= N) PV32[((size_t)w * N + g) * m + (p - N)] = (float)v[u];
+                if (prec >= 2 && p >= N) PV32[((size_t)w * N + g) * m + (p - N)] = (float)v[u];
             }
         }
-    } else if (row && prec == 2) {
+    } else if (row && prec >= 2) {
         for (int p = 0; p < m; ++p) PV32[((size_t)w * N + g) * m + p] = (float)Phw[g * no + N + p];
     }
     double a[N];
@@ -670,19 +670,29 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
     const int WT = S.WT, tw = w / WT, lw = w % WT;
     float *__restrict__ Tp = I.Tp32 + (size_t)tw * n * m * WT + lw;
     float *__restrict__ g32 = I.ev32 + (size_t)tw * 4 * m * WT + lw;
+    const bool ksum64 = I.prec == 3;
     for (int t = wave; t < RT * CT; t += 4) {
         const int rt = t / CT, ct = t - rt * CT;
-        // each MFMA multiplies FP32 operands over a K-block of 4 with FP32
-        // accumulation; the K-blocks are summed in FP64 (FP32 accumulation
-        // over all of K = n left the worst-conditioned walkers above 1e-5)
+        // MIXED_GEMM: one chain of MFMAs over all of K with FP32 accumulation.
+        // MIXED_GEMM_KSUM64: each MFMA multiplies one K-block of 4 into a zero
+        // FP32 accumulator and the K-blocks are summed in FP64.
         double acc64[4] = {0.0, 0.0, 0.0, 0.0};
+        floatx4 acc32 = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int kk = 0; kk < kp; kk += 4) {
             const float a = As[(rt * 16 + lr) * lda + kk + lk];
             const float b = Bs[(kk + lk) * mp + ct * 16 + lr];
-            const floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-            const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, z, 0, 0, 0);
+            if (ksum64) {
+                const floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, z, 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc64[i] += (double)acc[i];
+                for (int i = 0; i < 4; ++i) acc64[i] += (double)acc[i];
+            } else {
+                acc32 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc32, 0, 0, 0);
+            }
+        }
+        if (!ksum64) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc64[i] = (double)acc32[i];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -700,7 +710,7 @@ k_gemm_mixed(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ mov
 hipError_t launch_propose(hipStream_t st, const InstDev *d_insts, int n_inst, int maxW,
                           const MoveArgs *d_moves, const MoveArgs &m1, int prec, int nmax,
                           int mmax, int WT, int max_tiles, int split) {
-    if (prec == 2) {
+    if (prec >= 2) {
         dim3 grid((maxW + 3) / 4, n_inst);
         hipLaunchKernelGGL(k_propose_mixed, grid, dim3(256), 0, st, d_insts, d_moves, m1);
         hipError_t e = hipGetLastError();
@@ -870,7 +880,7 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
             if (!acc_s[l]) continue;
             const double v = nrow[(size_t)w * I.nomax + p];
             S.Phi[((size_t)w * n + row) * no + p] = v;
-            if (I.prec == 2 && p >= n) S.PhiV32[((size_t)w * n + row) * m + (p - n)] = (float)v;
+            if (I.prec >= 2 && p >= n) S.PhiV32[((size_t)w * n + row) * m + (p - n)] = (float)v;
         }
     }
     if (part == 0 && tid < nw && acc_s[tid]) {

@@ -652,7 +652,7 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
         S.B = cv.take<double>((size_t)W * sp.n * sp.n);
         S.T = prec == 0 ? cv.take<double>(Wp * sp.n * sp.m) : nullptr;
         S.T32 = prec != 0 ? cv.take<float>(Wp * sp.n * sp.m) : nullptr;
-        S.PhiV32 = prec == 2 ? cv.take<float>((size_t)W * sp.n * sp.m) : nullptr;
+        S.PhiV32 = prec >= 2 ? cv.take<float>((size_t)W * sp.n * sp.m) : nullptr;
         S.logdet = cv.take<double>(W);
         S.sgn = cv.take<double>(W);
         S.R = cv.take<double>(Wp * sp.U);
@@ -700,7 +700,7 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
     h.ev32 = prec != 0 ? cv.take<float>(Wq * 4 * mmax) : nullptr;
     h.cc32 = prec != 0 ? cv.take<float>(Wq * nmax) : nullptr;
     h.Tp32 = prec != 0 ? cv.take<float>(Wq * nmax * mmax) : nullptr;
-    h.Ap32 = prec == 2 ? cv.take<float>((size_t)W * (nmax + 4) * nmax) : nullptr;
+    h.Ap32 = prec >= 2 ? cv.take<float>((size_t)W * (nmax + 4) * nmax) : nullptr;
     h.st = cv.take<int32_t>(W);
     h.counter = cv.take<int32_t>(64);
     h.Lnew = cv.take<double>(W);
@@ -905,7 +905,7 @@ mde_status mde_create(const mde_desc *desc, void *hip_stream, mde_ctx **out) {
     if (desc->max_walkers < 1 || desc->max_order < 1 || desc->max_order > MDE_MAX_ORDER)
         return MDE_INVALID;
     if (desc->precision != MDE_FP64 && desc->precision != MDE_MIXED &&
-        desc->precision != MDE_MIXED_GEMM)
+        desc->precision != MDE_MIXED_GEMM && desc->precision != MDE_MIXED_GEMM_KSUM64)
         return MDE_INVALID;
     mde_ctx *c = new (std::nothrow) mde_ctx();
     if (!c) return MDE_NOMEM;

@@ -341,15 +341,17 @@ def water_like(cfg: int = 1, W: Optional[int] = None, n_det: Optional[int] = Non
 
 def molecular(cfg: int = 3, W: int = 2048, n_det: int = 100000, n_moves: int = 64,
               n: int = 32, m: int = 224, nb: int = 512, n_nuc: int = 20,
-              box: float = 12.0) -> Workload:
+              box: float = 12.0, electron_order=None) -> Workload:
     """Molecular-shaped system: n electrons per spin, n + m orbitals from nb
-    s-Gaussians on n_nuc nuclei uniform in a box of side ``box`` bohr."""
+    s-Gaussians on n_nuc nuclei uniform in a box of side ``box`` bohr.
+    electron_order: the moving electron of each move (default: move s moves
+    electron s mod 2n)."""
     rs = _streams((cfg,))
     nuclei = rs["nuclei"].uniform(0.0, box, size=(n_nuc, 3))
     sysm, rs, meta = make_system((cfg,), (n, n), (m, m), nuclei, nb, n_det,
                                  streams=rs)
     pos = draw_positions(rs["electrons"], nuclei, W, 2 * n)
-    mv = draw_moves(rs["moves"], rs["accept"], n_moves, W, 2 * n, 0.3)
+    mv = draw_moves(rs["moves"], rs["accept"], n_moves, W, 2 * n, 0.3, electron_order)
     meta.update(dict(W=W, n_moves=n_moves, key=[cfg]))
     return Workload(f"molecular n={n} m={m} ndet={n_det}", sysm, Walkers(pos), mv, meta)
 

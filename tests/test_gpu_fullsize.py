@@ -4,22 +4,24 @@ walker at a time:
 
 * water-like batched (5+5 electrons, 10 000 determinants, 4 096 walkers, FP64),
   one full sweep with the autotuned plan, 32 walkers spread over the tiles;
-* molecular-shaped mixed precision (n = 32, m = 224, 100 000 determinants,
-  2 048 walkers), both mixed forms and FP64, three walkers per move;
+* molecular-shaped (n = 32, m = 224, 100 000 determinants, 2 048 walkers),
+  FP64 and the three FP32-table forms, 32 walkers x 10 moves against stored
+  oracle values;
 * the adjoint on the water-like system (1 024 walkers, FP64), every walker;
 * the uneven batch (64 instances, n = 5..64, m = 4n, 10^2..2*10^5
   determinants, 256 walkers each) in one group launch, FP64, sampled
   (instance, walker) pairs.
 
-Gates as in the other parity tests: FP64 1e-10 under the condition-scaled
-scale; mixed forms 1e-4 at the maximum."""
+Gates as in the other parity tests: FP64 1e-10 under the condition-aware
+scale; FP32-table forms 1e-5 under the first-order FP32-entry scale."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import synth
-from tests._gpu import dev, gpu_orbitals, make_ctx, say, scaled_err
+from tests._gpu import (MIXED_TOL, dev, gpu_orbitals, make_ctx, output_errors, report_errors, say,
+                        scaled_err)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -65,27 +67,55 @@ def test_water_batched_full_size():
         pos[acc, e] = new_r[acc]
 
 
-@pytest.mark.parametrize("precision", ["mixed", "mixed_gemm", "fp64"])
+def _golden_module():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "make_molecular_sample.py")
+    spec = importlib.util.spec_from_file_location("make_molecular_sample", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_gemm", "mixed_gemm_ksum64"])
 def test_molecular_full_size(precision):
-    wl = synth.molecular(3, W=2048, n_det=100000, n_moves=2)
+    """n = 32, m = 224, 100 000 determinants, 2 048 walkers, default launch
+    plan: 10 moves alternating the spins, 32 sampled walkers (one per
+    64-walker tile) against the oracle's stored values
+    (tests/golden/molecular_n32_sample.npz, written by the oracle alone)."""
+    gm = _golden_module()
+    g = np.load(gm.OUT, allow_pickle=False)
+    wl = gm.workload()
+    assert str(g["fingerprint"]) == gm.fingerprint(wl), "generator drifted: rewrite the golden file"
     s = wl.system
     ctx = make_ctx(wl, precision=precision)
-    say(f"n=32 full size {precision} plan", ctx.get_plan(0))
+    say(f"n=32 full size {precision} plan", ctx.get_plan(0), ctx.get_plan(1))
     pos = wl.walkers.pos.copy()
-    ou, od = gpu_orbitals(ctx, pos)
-    ctx.init(ou, od)
-    sample = np.array([0, 1023, 2047])
-    tol = 1e-10 if precision == "fp64" else 1e-4
-    for k in range(2):
-        e = int(wl.moves.electron[k])
+    ctx.init(*gpu_orbitals(ctx, pos))
+    sample = g["sample"]
+    scaled_all, plain_all = [], []
+    for k, e in enumerate(g["electrons"]):
+        e = int(e)
         new_r = pos[:, e] + wl.moves.disp[k]
         ratio, grad, lap, st = ctx.propose(e, ctx.sgauss_eval(ctx.spin_of(e), dev(new_r)))
         mask = wl.moves.accept_half[k]
         ctx.accept(e, dev(mask, torch.uint8))
+        assert not st.cpu().numpy()[sample].any()
+        ref = dict(ratio=g["ratio"][k], grad=g["grad"][k], lap=g["lap"][k],
+                   scale_ratio=g["sc_ratio"][k], scale_grad=g["sc_grad"][k], scale_lap=g["sc_lap"][k])
+        ms = dict(round=g["x_round"][k], gemm=g["x_gemm"][k])
         got = (ratio.cpu().numpy()[sample], grad.cpu().numpy()[sample], lap.cpu().numpy()[sample])
-        _check_move(s, pos[sample].copy(), e, new_r[sample], got, tol, f"{precision} move {k}")
+        sc, pl = output_errors(precision, got, ref, ms)
+        scaled_all.append(sc)
+        plain_all.append(pl)
         acc = mask.astype(bool)
         pos[acc, e] = new_r[acc]
+    scaled_all = np.concatenate(scaled_all)
+    plain_all = np.concatenate(plain_all)
+    report_errors(f"n=32 full size {precision}", scaled_all, plain_all)
+    tol = 1e-10 if precision == "fp64" else MIXED_TOL
+    assert scaled_all.max() <= tol, (precision, scaled_all.max(axis=0))
 
 
 def test_adjoint_full_size():
