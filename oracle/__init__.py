@@ -57,7 +57,8 @@ def lib():
         L.oracle_tables_batch.argtypes = ([C.c_int] * 5 + [_dp, _dp] + exc + exc +
                                           [C.c_int64, _dp, _ip, _ip, _dp, _dp, _dp, _dp])
         L.oracle_mixed_scales_batch.argtypes = ([C.c_int] * 5 + [_dp, _dp, C.c_int, _dp] + exc + exc +
-                                                [C.c_int64, _dp, _ip, _ip, _dp, _dp])
+                                                [C.c_int64, _dp, _ip, _ip, C.c_void_p, C.c_void_p,
+                                                 C.c_void_p, _dp, _dp])
         L.oracle_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -257,16 +258,19 @@ def tables(sysm, T_up: np.ndarray, T_dn: np.ndarray, coef=None):
 # error scales of the FP32-table forms
 # ---------------------------------------------------------------------------
 
-def mixed_scales(sysm, pos: np.ndarray, e: int, new_r: np.ndarray, coef=None):
+def mixed_scales(sysm, pos: np.ndarray, e: int, new_r: np.ndarray, coef=None, err=None):
     """First-order error scales of one proposed move (as ``move``) for forms
     that keep table entries in FP32.  A relative perturbation eps of every
     FP32-stored entry moves each output x by at most eps * X to first order.
 
-    Returns ``round`` [W, 5] (entries rounded to FP32: E = |entry|),
-    ``gemm`` [W, 5] (entries formed by an FP32 product of A^-1 and Phi_V:
-    E = |A^-1| |Phi_V|), columns (ratio, d/dx, d/dy, d/dz, laplacian), and
-    ``vals`` [W, 5], the same outputs computed through the tables (pinned
-    against ``move``)."""
+    Returns ``round`` [W, 5] (entries rounded to FP32: E = |entry|, or the
+    propagated magnitudes ``err`` = (err_up [W, n, m], err_dn) of tables
+    kept in FP32 across commits), ``gemm`` [W, 5] (entries formed by an FP32
+    product of A^-1 and Phi_V: E = |A^-1| |Phi_V|), columns (ratio, d/dx,
+    d/dy, d/dz, laplacian), ``vals`` [W, 5], the same outputs computed
+    through the tables (pinned against ``move``), and ``err_next``
+    [W, n, m], the moving spin's table magnitudes after a commit of this
+    move (only with ``err``)."""
     pos = _f64(pos)
     W = pos.shape[0]
     nu, nd = sysm.n_elec
@@ -278,10 +282,56 @@ def mixed_scales(sysm, pos: np.ndarray, e: int, new_r: np.ndarray, coef=None):
     coef = _f64(sysm.coef if coef is None else coef)
     out = np.empty((W, 2, 5))
     vals = np.empty((W, 5))
+    e_ms = e_os = e_next = None
+    if err is not None:
+        e_ms = _f64(err[spin])
+        e_os = _f64(err[1 - spin])
+        e_next = np.empty_like(e_ms)
+    ptr = lambda a: None if a is None else a.ctypes.data  # noqa: E731
     rc = lib().oracle_mixed_scales_batch(W, nu, nd, nou, nod, ou, od, int(e), blk,
                                          *_exc_args(ex_u), *_exc_args(ex_d),
                                          int(coef.shape[0]), coef, _i32(sysm.det_up),
-                                         _i32(sysm.det_dn), out, vals)
+                                         _i32(sysm.det_dn), ptr(e_ms), ptr(e_os), ptr(e_next),
+                                         out, vals)
     if rc != 0:
         raise RuntimeError("oracle_mixed_scales_batch failed (singular reference?)")
-    return dict(round=out[:, 0].copy(), gemm=out[:, 1].copy(), vals=vals)
+    res = dict(round=out[:, 0].copy(), gemm=out[:, 1].copy(), vals=vals)
+    if err is not None:
+        res["err_next"] = e_next
+    return res
+
+
+def table_magnitudes(sysm, pos: np.ndarray):
+    """|T_V| of both spins at positions pos [W, n_tot, 3]: the entry
+    magnitudes of tables just computed from scratch and rounded once
+    (T = A^-1 Phi_V, Sec. III)."""
+    ou, od = walker_orbitals(sysm, pos)
+    out = []
+    for s, orb in ((0, ou), (1, od)):
+        n = sysm.n_elec[s]
+        T = np.stack([np.linalg.solve(o[:, 0, :n], o[:, 0, n:]) for o in orb])
+        out.append(np.abs(T))
+    return out
+
+
+class StoredTableErrors:
+    """Entrywise first-order error magnitudes (units of eps) of the two
+    spins' tables kept in FP32 across commits, along a trajectory: one
+    rounding after a from-scratch evaluation, propagated through each
+    committed table update (see oracle_mixed_scales_batch)."""
+
+    def __init__(self, sysm, pos):
+        self.sysm = sysm
+        self.err = table_magnitudes(sysm, pos)
+
+    def scales(self, pos, e, new_r):
+        self._last = mixed_scales(self.sysm, pos, e, new_r, err=self.err)
+        self._spin = 0 if e < self.sysm.n_elec[0] else 1
+        return self._last
+
+    def commit(self, accepted):
+        acc = np.asarray(accepted, bool)
+        self.err[self._spin][acc] = self._last["err_next"][acc]
+
+    def refresh(self, pos):
+        self.err = table_magnitudes(self.sysm, pos)

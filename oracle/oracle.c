@@ -524,6 +524,15 @@ int oracle_tables_batch(int W, int n_up, int n_dn, int m_up, int m_dn,
  * rounding of the entries, kind 1: product-formed entries.  vals[w][5] = the
  * same outputs computed by this table route (pinned against the full-LU
  * route of oracle_mds_batch).
+ *
+ * Tables kept in FP32 across commits (the table update T' = T - c' q^T,
+ * q = a'^T T - phi'_V, applied to the stored T, Sec. III) carry the errors of
+ * earlier updates: an error dT of the stored table reaches T' as
+ * (I - c' a'^T) dT, c' = A'^-1 e_i.  With err_ms [n][m] and err_os the
+ * entrywise error magnitudes (in units of eps) of the stored tables of the
+ * moving and the other spin (NULL: one rounding, |T|), kind 0 uses E = err
+ * for the tables at R and E' = |I - c' a'^T| err_ms + |T'| for T', and
+ * err_out [n][m] receives E' (the stored table's magnitudes after a commit).
  */
 
 /* det and cofactor matrix of a k x k matrix (row-major) by LU of each minor */
@@ -578,9 +587,11 @@ static int spin_tables(int n, int no, const double *phi, double *B, double *T, d
     return 0;
 }
 
-/* ratio, P and P_E of every excitation of one spin from its table */
-static void spin_ratios(int n, int m, const double *T, const double *E, int nx, const int *off,
-                        const int *hs, const int *ps, double *R, double *P, double *PE)
+/* ratio of every excitation of one spin from its table, and P_E of it for
+ * two entry-magnitude arrays E0 and E1 */
+static void spin_ratios(int n, int m, const double *T, const double *E0, const double *E1, int nx,
+                        const int *off, const int *hs, const int *ps, double *R, double *P,
+                        double *PE)
 {
     double S[81], cof[81];
     for (int u = 0; u < nx; ++u) {
@@ -593,12 +604,18 @@ static void spin_ratios(int n, int m, const double *T, const double *E, int nx, 
         double a = 0.0, b = 0.0;
         for (int j = 0; j < k; ++j)
             for (int l = 0; l < k; ++l) {
-                a += fabs(S[j * k + l]) * fabs(cof[j * k + l]);
-                b += E[(size_t)h[j] * m + p[l] - n] * fabs(cof[j * k + l]);
+                a += E0[(size_t)h[j] * m + p[l] - n] * fabs(cof[j * k + l]);
+                b += E1[(size_t)h[j] * m + p[l] - n] * fabs(cof[j * k + l]);
             }
         P[u] = a;
         PE[u] = b;
     }
+}
+
+/* kind-0 error magnitudes of a stored table: given ones, or |T| */
+static void err_or_abs(int n, int m, const double *given, const double *T, double *E)
+{
+    for (size_t q = 0; q < (size_t)n * m; ++q) E[q] = given ? given[q] : fabs(T[q]);
 }
 
 static int mixed_walker(int n_up, int n_dn, int no_up, int no_dn, const double *orb_up,
@@ -606,6 +623,7 @@ static int mixed_walker(int n_up, int n_dn, int no_up, int no_dn, const double *
                         int nx_up, const int *off_up, const int *h_up, const int *p_up,
                         int nx_dn, const int *off_dn, const int *h_dn, const int *p_dn,
                         int64_t n_det, const double *coef, const int *iu, const int *id,
+                        const double *err_ms, const double *err_os, double *err_out,
                         double *out, double *vals)
 {
     const int ms = e < n_up ? 0 : 1, os = 1 - ms;
@@ -645,13 +663,30 @@ static int mixed_walker(int n_up, int n_dn, int no_up, int no_dn, const double *
         free(ph);
         /* restore B of the moving spin at R (not needed further) */
     }
+    double *K0 = malloc(sizeof(double) * (size_t)nmax * mmax);    /* kind 0, moving spin at R */
+    double *K0p = malloc(sizeof(double) * (size_t)nmax * mmax);   /* kind 0, T' */
+    double *K0o = malloc(sizeof(double) * (size_t)nmax * mmax);   /* kind 0, other spin */
+    double cp[OR_MAXN];
     if (rc == 0) {
-        spin_ratios(n, m, T, E, nx[ms], off_s[ms], h_s[ms], p_s[ms], R, R + nx[ms], R + 2 * nx[ms]);
-        spin_ratios(n, m, Tp, Ep, nx[ms], off_s[ms], h_s[ms], p_s[ms], Rp, Rp + nx[ms], Rp + 2 * nx[ms]);
-        spin_ratios(n2, m2, To, Eo, nx[os], off_s[os], h_s[os], p_s[os], Ro, Ro + nx[os], Ro + 2 * nx[os]);
-        /* derivative factors at R' */
-        double cp[OR_MAXN], rho[4], g[4][256], Eg[4][256];
         for (int r = 0; r < n; ++r) cp[r] = Bp[r * n + row];
+        err_or_abs(n, m, err_ms, T, K0);
+        err_or_abs(n2, m2, err_os, To, K0o);
+        /* T' inherits the stored table's errors through I - c' a'^T */
+        for (int r = 0; r < n; ++r)
+            for (int p = 0; p < m; ++p) {
+                double acc = fabs(Tp[(size_t)r * m + p]);
+                for (int k = 0; k < n; ++k) {
+                    const double pr = fabs((r == k ? 1.0 : 0.0) - cp[r] * phi2[(size_t)row * no + k]);
+                    acc += pr * K0[(size_t)k * m + p];
+                }
+                K0p[(size_t)r * m + p] = acc;
+            }
+        if (err_out) memcpy(err_out, K0p, sizeof(double) * (size_t)n * m);
+        spin_ratios(n, m, T, K0, E, nx[ms], off_s[ms], h_s[ms], p_s[ms], R, R + nx[ms], R + 2 * nx[ms]);
+        spin_ratios(n, m, Tp, K0p, Ep, nx[ms], off_s[ms], h_s[ms], p_s[ms], Rp, Rp + nx[ms], Rp + 2 * nx[ms]);
+        spin_ratios(n2, m2, To, K0o, Eo, nx[os], off_s[os], h_s[os], p_s[os], Ro, Ro + nx[os], Ro + 2 * nx[os]);
+        /* derivative factors at R' */
+        double rho[4], g[4][256], Eg[4][256], Eg0[4][256];
         for (int a = 0; a < 4; ++a) {
             const double *d = blk + (size_t)(1 + a) * no;
             double ra = 0.0, ea[OR_MAXN];
@@ -670,6 +705,10 @@ static int mixed_walker(int n_up, int n_dn, int no_up, int no_dn, const double *
                 }
                 g[a][p] = t;
                 Eg[a][p] = fabs(d[n + p]) + ee;
+                /* g^a = d^a_V - d^a_O^T T' carries the stored table's error */
+                double e0 = fabs(t);
+                for (int r = 0; r < n; ++r) e0 += fabs(d[r]) * K0p[(size_t)r * m + p];
+                Eg0[a][p] = e0;
             }
         }
         /* bordered determinants per excitation of the moving spin */
@@ -688,7 +727,7 @@ static int mixed_walker(int n_up, int n_dn, int no_up, int no_dn, const double *
                 const double d = det_cof(K, Bo, cof);
                 double pa = 0.0, pb = 0.0;
                 for (int l = 0; l < k; ++l) {
-                    pa += fabs(Bo[1 + l]) * fabs(cof[1 + l]);
+                    pa += Eg0[a][p[l] - n] * fabs(cof[1 + l]);
                     pb += Eg[a][p[l] - n] * fabs(cof[1 + l]);
                 }
                 for (int j = 0; j < k; ++j) {
@@ -697,7 +736,7 @@ static int mixed_walker(int n_up, int n_dn, int no_up, int no_dn, const double *
                     pb += cc;
                     for (int l = 0; l < k; ++l) {
                         const double cf = fabs(cof[(1 + j) * K + 1 + l]);
-                        pa += fabs(Bo[(1 + j) * K + 1 + l]) * cf;
+                        pa += K0p[(size_t)h[j] * m + p[l] - n] * cf;
                         pb += Ep[(size_t)h[j] * m + p[l] - n] * cf;
                     }
                 }
@@ -737,7 +776,7 @@ static int mixed_walker(int n_up, int n_dn, int no_up, int no_dn, const double *
         }
     }
     free(phi); free(phi2); free(B); free(Bp); free(T); free(E); free(Tp); free(Ep);
-    free(To); free(Eo); free(R); free(Rp); free(Ro); free(G);
+    free(To); free(Eo); free(R); free(Rp); free(Ro); free(G); free(K0); free(K0p); free(K0o);
     return rc ? 1 : 0;
 }
 
@@ -747,17 +786,23 @@ int oracle_mixed_scales_batch(int W, int n_up, int n_dn, int no_up, int no_dn,
                               int nx_up, const int *off_up, const int *h_up, const int *p_up,
                               int nx_dn, const int *off_dn, const int *h_dn, const int *p_dn,
                               int64_t n_det, const double *coef, const int *iu, const int *id,
+                              const double *err_ms, const double *err_os, double *err_out,
                               double *out, double *vals)
 {
     int err = 0;
     const size_t su = (size_t)n_up * 5 * no_up, sd = (size_t)n_dn * 5 * no_dn;
-    const size_t sb = (size_t)5 * (e < n_up ? no_up : no_dn);
+    const int ms = e < n_up ? 0 : 1;
+    const size_t sb = (size_t)5 * (ms == 0 ? no_up : no_dn);
+    const size_t em = ms == 0 ? (size_t)n_up * (no_up - n_up) : (size_t)n_dn * (no_dn - n_dn);
+    const size_t eo = ms == 0 ? (size_t)n_dn * (no_dn - n_dn) : (size_t)n_up * (no_up - n_up);
     if (n_up > OR_MAXN || n_dn > OR_MAXN || no_up - n_up > 256 || no_dn - n_dn > 256) return -1;
 #pragma omp parallel for schedule(dynamic) reduction(|: err)
     for (int w = 0; w < W; ++w)
         err |= mixed_walker(n_up, n_dn, no_up, no_dn, orb_up + w * su, orb_dn + w * sd, e,
                             blk + w * sb, nx_up, off_up, h_up, p_up, nx_dn, off_dn, h_dn, p_dn,
-                            n_det, coef, iu, id, out + (size_t)w * 10, vals + (size_t)w * 5);
+                            n_det, coef, iu, id, err_ms ? err_ms + w * em : NULL,
+                            err_os ? err_os + w * eo : NULL, err_out ? err_out + w * em : NULL,
+                            out + (size_t)w * 10, vals + (size_t)w * 5);
     return err ? -1 : 0;
 }
 

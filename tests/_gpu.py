@@ -52,9 +52,10 @@ def scaled_err(x, ref, scale):
     return np.abs(x - ref) / scale
 
 
-# FP32-table forms and the first-order scale kind that bounds them: entries
-# rounded to FP32 (rank-one table updates), or formed by an FP32 product of
-# A^-1 and Phi_V (tables rebuilt by the MFMA GEMM)
+# FP32-table forms and the first-order scale kind that bounds them: tables
+# kept in FP32 across commits (rank-one table updates; pass the scales of
+# oracle.StoredTableErrors along the trajectory), or entries formed by an
+# FP32 product of A^-1 and Phi_V (tables rebuilt by the MFMA GEMM)
 MIXED_SCALE_KIND = {"mixed": "round", "mixed_gemm": "gemm", "mixed_gemm_ksum64": "gemm"}
 MIXED_TOL = 1e-5
 

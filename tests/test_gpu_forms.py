@@ -20,6 +20,8 @@ def _traj(wl, ctx, n_moves, precision, mask_key="accept_half"):
     ctx.init(ou, od)
     scaled, plain = [], []
     masks = getattr(wl.moves, mask_key)
+    n_tot = sum(s.n_elec)
+    track = oracle.StoredTableErrors(s, pos) if precision != "fp64" else None
     for k in range(n_moves):
         e = int(wl.moves.electron[k])
         spin = 0 if e < s.n_elec[0] else 1
@@ -27,7 +29,7 @@ def _traj(wl, ctx, n_moves, precision, mask_key="accept_half"):
         ratio, grad, lap, st = ctx.propose(e, ctx.sgauss_eval(spin, dev(new_r)))
         ctx.accept(e, dev(masks[k], torch.uint8))
         ref = oracle.move(s, pos, e, new_r)
-        ms = None if precision == "fp64" else oracle.mixed_scales(s, pos, e, new_r)
+        ms = track.scales(pos, e, new_r) if track else None
         a, b = output_errors(precision, (ratio.cpu().numpy(), grad.cpu().numpy(), lap.cpu().numpy()),
                              ref, ms)
         scaled.append(a)
@@ -35,6 +37,10 @@ def _traj(wl, ctx, n_moves, precision, mask_key="accept_half"):
         assert np.all(st.cpu().numpy() == 0), (k, st)
         acc = masks[k].astype(bool)
         pos[acc, e] = new_r[acc]
+        if track:
+            track.commit(acc)
+            if (k + 1) % n_tot == 0:     # the library's from-scratch refresh
+                track.refresh(pos)
     return np.concatenate(scaled), np.concatenate(plain)
 
 
@@ -144,6 +150,8 @@ def test_group_matches_oracle_and_single_contexts(by_tile, precision):
         ou, od = gpu_orbitals(c, p)
         c.init(ou, od)
         t.init(ou, od)
+    tracks = [oracle.StoredTableErrors(w.system, p) if precision != "fp64" else None
+              for w, p in zip(wls, pos)]
     for k in range(6):
         es, news, outs, masks = [], [], [], []
         for i, (c, w, p) in enumerate(zip(ctxs, wls, pos)):
@@ -165,11 +173,15 @@ def test_group_matches_oracle_and_single_contexts(by_tile, precision):
                 assert torch.equal(a, b), (k, i)
             new_r = p[:, es[i]] + w.moves.disp[k]
             ref = oracle.move(w.system, p, es[i], new_r)
-            ms = None if precision == "fp64" else oracle.mixed_scales(w.system, p, es[i], new_r)
+            ms = tracks[i].scales(p, es[i], new_r) if tracks[i] else None
             sc, _ = output_errors(precision, tuple(o.cpu().numpy() for o in outs[i][:3]), ref, ms)
             assert sc.max() <= tol, (k, i, sc.max(axis=0))
             acc = w.moves.accept_half[k].astype(bool)
             p[acc, es[i]] = new_r[acc]
+            if tracks[i]:
+                tracks[i].commit(acc)
+                if (k + 1) % sum(w.system.n_elec) == 0:
+                    tracks[i].refresh(p)
 
 
 def test_graph_replay_matches_eager():

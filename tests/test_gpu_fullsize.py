@@ -85,8 +85,7 @@ def test_molecular_full_size(precision):
     64-walker tile) against the oracle's stored values
     (tests/golden/molecular_n32_sample.npz, written by the oracle alone)."""
     gm = _golden_module()
-    g = np.load(gm.OUT, allow_pickle=False)
-    wl = gm.workload()
+    wl, g = gm.load()
     assert str(g["fingerprint"]) == gm.fingerprint(wl), "generator drifted: rewrite the golden file"
     s = wl.system
     ctx = make_ctx(wl, precision=precision)

@@ -250,8 +250,9 @@ def test_group_member_plan_change_rebuilds():
         c.init(*gpu_orbitals(c, w.walkers.pos))
     wt = ctxs[0].get_plan(0)["walker_tile"]
     item = ctxs[0].get_plan(0)["item_exc"]
-    ctxs[0].set_plan(0, walker_tile=wt, item_exc=max(4, item // 3))
-    ctxs[0].set_plan(1, walker_tile=wt, item_exc=max(4, item // 3))
+    # coarser items: fewer than the workspace was sized for
+    ctxs[0].set_plan(0, walker_tile=wt, item_exc=2 * item)
+    ctxs[0].set_plan(1, walker_tile=wt, item_exc=2 * item)
     ctxs[0].init(*gpu_orbitals(ctxs[0], wls[0].walkers.pos))
     es = [int(w.moves.electron[0]) for w in wls]
     blks = [c.sgauss_eval(c.spin_of(e), dev(w.walkers.pos[:, e] + w.moves.disp[0]))

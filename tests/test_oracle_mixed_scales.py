@@ -49,14 +49,23 @@ def _fp32_route(sysm, pos, e, new_r, kind):
             tabs[key] = (B, T, phi)
         n = sysm.n_elec[ms]
         Bp, Tp, phip = tabs["Rp"]
-        Bp_exact_T = Bp @ phip[:, n:]
         cp = _f32(Bp[:, row])
         rho_a, g = [], []
+        if kind == "round":
+            # the rank-one form: T' = T - c' q^T in FP64 from the stored FP32
+            # table, q = a'^T T - phi'_V, then rounded; g^a = w^a + (k^a/rho) q
+            B0, T0 = tabs["R"][0], tabs["R"][1]
+            c = B0[:, row]
+            a_new = blk[w, 0]
+            rho = a_new[:n] @ c
+            q = a_new[:n] @ T0 - a_new[n:]
+            Tp = _f32(T0 - np.outer(c / rho, q))
         for a in range(4):
             d = blk[w, 1 + a]
             rho_a.append(d[:n] @ Bp[:, row])
             if kind == "round":
-                g.append(_f32(d[n:] - d[:n] @ Bp_exact_T))
+                wa = d[n:] - d[:n] @ T0
+                g.append(_f32(wa + (d[:n] @ c) / rho * q))
             else:
                 ea = (d[:n] @ Bp).astype(np.float32)
                 g.append(_f32(d[n:] - (ea @ phip[:, n:].astype(np.float32)).astype(np.float64)))
@@ -133,16 +142,74 @@ def test_table_route_values_equal_full_lu_route():
         assert np.all(np.abs(v[:, 4] - ref["lap"]) <= 1e-12 * ref["scale_lap"])
 
 
-def test_single_determinant_of_singles_closed_form():
-    """One determinant, a single excitation in each spin: each ratio is one
-    table entry (P = |entry|), so the ratio's scale is 4 |ratio| (two
-    entries at R', two at R, each weighing |x|)."""
+def test_single_determinant_closed_form():
+    """One determinant: the reference in the moving (up) spin and a single
+    excitation in the other.  Every output is then proportional to one table
+    entry of the other spin (P = |entry|), read at R and R' alike, so each
+    scale is 2 |x|: X = |x| (1 + 1) for the ratio, (|x| + |x|) for the
+    derivatives (the reference's derivative factor rho^a is FP64)."""
     wl = synth.water_like(2, W=6, n_det=400, n_moves=2)
     s = wl.system
     ex_u, ex_d = s.exc
-    I = next(i for i in range(s.n_det) if ex_u.order(s.det_up[i]) == 1 and ex_d.order(s.det_dn[i]) == 1)
+    I = next(i for i in range(s.n_det) if ex_u.order(s.det_up[i]) == 0 and ex_d.order(s.det_dn[i]) == 1)
     one = synth.with_coef(s, np.where(np.arange(s.n_det) == I, 1.0, 0.0))
     pos = wl.walkers.pos
     new_r = pos[:, 2] + wl.moves.disp[0]
     m = oracle.mixed_scales(one, pos, 2, new_r)
-    assert np.allclose(m["round"][:, 0], 4 * np.abs(m["vals"][:, 0]), rtol=1e-12)
+    for kind in ("round", "gemm"):
+        X = m[kind]
+        if kind == "round":
+            assert np.allclose(X, 2 * np.abs(m["vals"]), rtol=1e-12)
+        # the product-formed entry's magnitude |A^-1| |Phi_V| bounds |entry|
+        assert np.all(X >= 2 * np.abs(m["vals"]) * (1 - 1e-12))
+
+
+def test_propagated_errors_cover_a_committed_sequence():
+    """Tables kept in FP32 across commits (the rank-one form): along a
+    sequence of committed moves the float32 emulation stays within the
+    scale whose entry magnitudes are propagated by StoredTableErrors."""
+    wl = synth.molecular(3, W=3, n_det=150, n_moves=6, n=12, m=40, nb=64, n_nuc=6, box=6.0)
+    s = wl.system
+    pos = wl.walkers.pos.copy()
+    nu = s.n_elec[0]
+    # stored FP32 tables of both spins, emulated along the sequence
+    ou, od = oracle.walker_orbitals(s, pos)
+    T32 = [np.stack([_f32(np.linalg.solve(o[:, 0, :s.n_elec[sp]], o[:, 0, s.n_elec[sp]:]))
+                     for o in orb]) for sp, orb in ((0, ou), (1, od))]
+    B = [np.stack([np.linalg.inv(o[:, 0, :s.n_elec[sp]]) for o in orb]) for sp, orb in ((0, ou), (1, od))]
+    track = oracle.StoredTableErrors(s, pos)
+    worst = 0.0
+    for k, e in enumerate([0, 3, 14, 5, 20, 1]):
+        sp = 0 if e < nu else 1
+        row = e if sp == 0 else e - nu
+        n = s.n_elec[sp]
+        new_r = pos[:, e] + wl.moves.disp[k]
+        blk = oracle.orbitals(s, sp, new_r)
+        ref = oracle.move(s, pos, e, new_r)
+        X = track.scales(pos, e, new_r)["round"]
+        for w in range(pos.shape[0]):
+            c = B[sp][w][:, row]
+            a = blk[w, 0]
+            rho = a[:n] @ c
+            q = a[:n] @ T32[sp][w] - a[n:]
+            Tp = _f32(T32[sp][w] - np.outer(c / rho, q))
+            ex = s.exc[sp]
+            def dets(T, spin):
+                exs = s.exc[spin]
+                nn = s.n_elec[spin]
+                return np.array([np.linalg.det(T[np.ix_(exs.get(u)[0], exs.get(u)[1] - nn)])
+                                 if exs.order(u) else 1.0 for u in range(exs.n_exc)])
+            R0, R1, Ro = dets(T32[sp][w], sp), dets(Tp, sp), dets(T32[1 - sp][w], 1 - sp)
+            um = s.det_up if sp == 0 else s.det_dn
+            uo = s.det_dn if sp == 0 else s.det_up
+            ratio = rho * np.sum(s.coef * R1[um] * Ro[uo]) / np.sum(s.coef * R0[um] * Ro[uo])
+            rel = abs(ratio - ref["ratio"][w]) / (U32 * X[w, 0])
+            worst = max(worst, rel)
+            assert rel <= 1.5, (k, w, rel)
+            if wl.moves.accept[k, w]:
+                T32[sp][w] = Tp
+                B[sp][w] = B[sp][w] - np.outer(c / rho, a[:n] @ B[sp][w] - np.eye(n)[row])
+        track.commit(wl.moves.accept[k])
+        pos[:, e] = new_r
+    assert worst > 1e-3
+
