@@ -2,8 +2,9 @@
 """Throughput of the multi-determinant table method on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,mixed]
+                    [--rows cfg3_fp64,...]
 
-Workload (headline): the water-like batched system -- 5 up + 5 down
+Headline workload: the water-like batched system -- 5 up + 5 down
 electrons, 5 occupied + 20 virtual orbitals per spin from 40 s-Gaussians on
 the three water nuclei, 10 000 determinants of orders 1-4, 4096 walkers, all
 inputs seeded and synthetic.  One step is one sweep: every electron proposes
@@ -16,10 +17,16 @@ Metric: walker.det/s = walkers x determinants x moves / time.  The JSON line
 also carries the roofline of the determinant kernel (bound by HBM: it streams
 every walker's CI weights once per move; its FP64 vector-ALU figure beside),
 the CPU oracle timed on a bounded sample of the same workload, and the other
-precision forms.  `--rows adjoint,uneven` adds two more rows of the path
-under "rows": the adjoint (forward from the tables + backward, 1024 walkers,
-FP64, with the oracle timed beside it) and 64 uneven instances moved
-together, one group launch per walker-tile size.
+precision forms.  Under "rows" (default: all of them) the other workloads of
+the path, each with its own roofline block and oracle baseline:
+
+* cfg3_*: molecular-shaped, n = 32 per spin, m = 224, 100 000 determinants,
+  2048 walkers, in the FP64 form and the FP32-table forms, with the error of
+  every output against stored oracle values (32 walkers x 10 moves);
+* cfg4_adjoint: forward from the tables + backward, 1024 walkers, FP64;
+* cfg5_uneven_*: 64 instances of uneven size (n = 5..64 per spin, m = 4n,
+  10^2..2x10^5 determinants, 256 walkers each) moved together, FP64 and the
+  rank-one FP32-table form.
 """
 from __future__ import annotations
 
@@ -55,16 +62,20 @@ def flops_per_launch(exc, W: int) -> float:
     return float(W) * sum(det_flops(int(k)) for k in orders if k > 0)
 
 
-def bytes_per_launch(exc, W: int, n: int, m: int, precision: str) -> float:
+def bytes_per_launch(exc, W: int, n: int, m: int, precision: str, fused: bool = True) -> float:
     """Algorithmic HBM bytes of one determinant-kernel launch: each walker's CI
     weight C_u of every excitation of the moving spin (8 B, read once), the
-    walker's inputs once and its output sums once.  FP64 form (the kernel
-    forms the proposal itself): T [n*m], the inverse [n*n], the new orbital
-    values and their gradient and laplacian [5(n+m)], six sums out.  Mixed
-    forms: FP32 T' [n*m], g^a [4m], c' [n], five sums out."""
+    walker's inputs once and its output sums once.  FP64 form with the
+    proposal formed in the kernel (n <= 8): T [n*m], the inverse [n*n], the
+    new orbital values and their gradient and laplacian [5(n+m)], six sums
+    out.  FP64 form with a separate proposal kernel: T [n*m], the e-terms
+    [5m], c [n], six sums out.  FP32-table forms: T' [n*m], g^a [4m], c' [n]
+    in FP32, five sums out."""
     U = int((exc.orders() > 0).sum())
     if precision == "fp64":
-        return float(W) * (8 * U + 8 * (n * m + n * n + 5 * (n + m)) + 6 * 8)
+        if fused:
+            return float(W) * (8 * U + 8 * (n * m + n * n + 5 * (n + m)) + 6 * 8)
+        return float(W) * (8 * U + 8 * (n * m + 5 * m + n) + 6 * 8)
     return float(W) * (8 * U + 4 * (n * m + 4 * m + n) + 5 * 8)
 
 
@@ -116,8 +127,10 @@ def build_context(wl, precision, stream, refresh_every):
     return ctx
 
 
-def run_form(wl, precision, steps, warmup, autotune=True, repeat=8):
-    """Time `steps` sweeps (one graph) of one precision form; returns a dict."""
+def run_form(wl, precision, steps, warmup, autotune=True, repeat=8, check=None):
+    """Time `steps` sweeps (one graph) of one precision form; returns a dict.
+    check(ctx) runs first on the bound context (e.g. a parity replay) and its
+    result is returned under "check"."""
     import torch
     s = wl.system
     W = wl.walkers.W
@@ -125,6 +138,7 @@ def run_form(wl, precision, steps, warmup, autotune=True, repeat=8):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         ctx = build_context(wl, precision, stream, refresh_every=n_tot)
+        checked = check(ctx) if check is not None else None
         pos = torch.as_tensor(wl.walkers.pos, device="cuda")
         nu = s.n_elec[0]
         ou = ctx.sgauss_eval(0, pos[:, :nu].contiguous())
@@ -201,7 +215,9 @@ def run_form(wl, precision, steps, warmup, autotune=True, repeat=8):
     ms_step = ms_total / steps
     wdets = W * s.n_det * n_tot
     fl = np.mean([flops_per_launch(s.exc[ctx.spin_of(m[0])], W) for m in moves])
-    by = np.mean([bytes_per_launch(s.exc[sp], W, s.n_elec[sp], s.n_orb[sp] - s.n_elec[sp], precision)
+    fused = precision == "fp64" and plan[0]["walker_tile"] == 64 and max(s.n_elec) <= 8
+    by = np.mean([bytes_per_launch(s.exc[sp], W, s.n_elec[sp], s.n_orb[sp] - s.n_elec[sp], precision,
+                                   fused)
                   for sp in (ctx.spin_of(m[0]) for m in moves)])
     det_avg_s = det_ms / max(det_n, 1) / 1e3
     return dict(precision=precision, ms_per_step=ms_step, value=wdets / (ms_step / 1e3),
@@ -211,22 +227,31 @@ def run_form(wl, precision, steps, warmup, autotune=True, repeat=8):
                 det_bytes_per_launch=by,
                 det_gbs=by / det_avg_s / 1e9 if det_n else None,
                 det_tflops=fl / det_avg_s / 1e12 if det_n else None, plan=plan,
-                status_bits=int(np.bitwise_or.reduce(st.ravel())) if st.size else 0)
+                status_bits=int(np.bitwise_or.reduce(st.ravel())) if st.size else 0,
+                check=checked)
 
 
-def cpu_baseline(wl, target_seconds=12.0):
+def cpu_baseline(wl, target_seconds=12.0, probe=64, max_moves=None):
     """The oracle on a bounded sample of the same workload (the first walkers,
-    the first moves of the sweep), on the host cores."""
+    the first moves of the sweep), on the host cores; max_moves=1: the first
+    move of the first `probe` walkers."""
     import oracle
     s = wl.system
     threads = oracle.num_threads()
     n_tot = sum(s.n_elec)
     # size the walker sample so that one sweep takes about target_seconds
-    probe = min(wl.walkers.W, 64)
+    probe = min(wl.walkers.W, probe)
     t0 = time.perf_counter()
     e = int(wl.moves.electron[0])
     oracle.move(s, wl.walkers.pos[:probe].copy(), e, wl.walkers.pos[:probe, e] + wl.moves.disp[0, :probe])
-    per_walker_move = (time.perf_counter() - t0) / probe
+    dt_probe = time.perf_counter() - t0
+    per_walker_move = dt_probe / probe
+    if dt_probe > 0.5 * target_seconds or max_moves == 1:
+        # one move of the probe sample is already the bounded sample
+        return dict(value=probe * s.n_det / dt_probe, unit="walker.det/s", cores=threads,
+                    kind="oracle",
+                    sample=f"{probe} walkers x 1 move of the same workload "
+                           f"(full-LU oracle, {dt_probe:.1f} s)")
     sample_w = int(min(wl.walkers.W, max(probe, target_seconds / (n_tot * per_walker_move))))
     pos = wl.walkers.pos[:sample_w].copy()
     moves = 0
@@ -243,6 +268,111 @@ def cpu_baseline(wl, target_seconds=12.0):
                 kind="oracle",
                 sample=f"{sample_w} walkers x {moves} moves of the same workload "
                        f"(full-LU oracle, {dt:.1f} s)")
+
+
+def roofline_block(kernel, achieved_bytes, seconds, flops=None, traffic=None, note=None):
+    """HBM roofline of one kernel from its algorithmic bytes per launch and its
+    measured average launch time (FP64 vector-ALU figure beside)."""
+    gbs = achieved_bytes / seconds / 1e9
+    out = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": gbs / PEAK_HBM_GBS, "traffic": traffic, "kernel": kernel,
+           "launch_us": seconds * 1e6, "bytes_per_launch": achieved_bytes}
+    if flops is not None:
+        tf = flops / seconds / 1e12
+        out["alu"] = {"achieved": tf, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                      "frac": tf / PEAK_FP64_VECTOR_TFLOPS, "flops_per_launch": flops}
+    if note:
+        out["note"] = note
+    return out
+
+
+# ---- molecular-shaped rows (n = 32, m = 224, 100 000 determinants) -------------
+
+GOLDEN_SCRIPT = os.path.join(ROOT, "tests", "golden", "make_molecular_sample.py")
+MIXED_KIND = {"mixed": "round", "mixed_gemm": "gemm", "mixed_gemm_ksum64": "gemm"}
+
+
+def golden_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_molecular_sample", GOLDEN_SCRIPT)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def molecular_workload():
+    """Sweep workload of the molecular-shaped system (64 moves, every electron
+    once) with the inputs the stored oracle sample was computed from."""
+    gm = golden_module()
+    g_wl, g = gm.load()
+    wl = synth_mod().molecular(3, W=2048, n_det=100000, n_moves=64)
+    wl.system = g_wl.system
+    return wl, g_wl, g
+
+
+def molecular_check(g_wl, g, precision):
+    """Replay of the stored sample's 10 moves on the bound context: the error
+    of every output of 32 walkers against the oracle's values (scaled as in
+    the parity tests, and plain relative)."""
+    import torch
+
+    def check(ctx):
+        pos = g_wl.walkers.pos.copy()
+        nu = g_wl.system.n_elec[0]
+        p = torch.as_tensor(pos, device="cuda")
+        ctx.init(ctx.sgauss_eval(0, p[:, :nu].contiguous()), ctx.sgauss_eval(1, p[:, nu:].contiguous()))
+        samp = g["sample"]
+        scaled, plain = [], []
+        for k, e in enumerate(g["electrons"]):
+            e = int(e)
+            new_r = pos[:, e] + g_wl.moves.disp[k]
+            blk = ctx.sgauss_eval(ctx.spin_of(e), torch.as_tensor(new_r, device="cuda"))
+            ratio, grad, lap, st = ctx.propose(e, blk)
+            mask = g_wl.moves.accept_half[k]
+            ctx.accept(e, torch.as_tensor(mask, dtype=torch.uint8, device="cuda"))
+            got = np.column_stack([ratio.cpu().numpy()[samp], grad.cpu().numpy()[samp],
+                                   lap.cpu().numpy()[samp]])
+            ref = np.column_stack([g["ratio"][k], g["grad"][k], g["lap"][k]])
+            if precision == "fp64":
+                sc = np.column_stack([g["sc_ratio"][k], g["sc_grad"][k], g["sc_lap"][k]])
+            else:
+                sc = g["x_" + MIXED_KIND[precision]][k]
+            d = np.abs(got - ref)
+            scaled.append(d / sc)
+            plain.append(d / np.abs(ref))
+            acc = mask.astype(bool)
+            pos[acc, e] = new_r[acc]
+        scaled = np.concatenate(scaled)
+        plain = np.concatenate(plain)
+        out = {"sample": "32 walkers x 10 moves (both spins) against stored oracle values",
+               "scale": "condition-aware" if precision == "fp64"
+               else "first-order FP32-table-entry scale (" + MIXED_KIND[precision] + ")",
+               "gate": 1e-10 if precision == "fp64" else 1e-5}
+        for nm, c in (("ratio", slice(0, 1)), ("grad", slice(1, 4)), ("lap", slice(4, 5))):
+            out[nm] = {"scaled_max": float(scaled[:, c].max()),
+                       "plain_rel_max": float(plain[:, c].max()),
+                       "plain_rel_median": float(np.median(plain[:, c])),
+                       "plain_rel_above_1e-5": f"{int((plain[:, c] > 1e-5).sum())}/{plain[:, c].size}"}
+        return out
+    return check
+
+
+def run_molecular(wl, g_wl, g, precision, steps, warmup, repeat=4):
+    r = run_form(wl, precision, steps, warmup, autotune=True, repeat=repeat,
+                 check=molecular_check(g_wl, g, precision))
+    s = wl.system
+    row = dict(value=r["value"], unit="walker.det/s", ms_per_step=r["ms_per_step"],
+               ms_per_move=r["ms_per_step"] / sum(s.n_elec),
+               workload=f"molecular-shaped: 32+32 electrons, 32+224 orbitals/spin, "
+                        f"{s.n_det} determinants (orders 1-4), {wl.walkers.W} walkers, {precision}; "
+                        "step = one sweep of 64 single-electron moves, 50% accepted",
+               precision=precision, plan=r["plan"], status_bits=r["status_bits"],
+               error=r["check"],
+               roofline=roofline_block(f"k_det<{'double' if precision == 'fp64' else 'float'}, propose, "
+                                       f"WT={r['plan'][0]['walker_tile']}>",
+                                       r["det_bytes_per_launch"], r["det_avg_us"] * 1e-6,
+                                       r["det_flops_per_launch"]))
+    return row
 
 
 def run_adjoint(steps, warmup, cpu=True):
@@ -279,9 +409,32 @@ def run_adjoint(steps, warmup, cpu=True):
         e1.record(stream)
         stream.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        # the backward alone (its kernels run on the context's stream)
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        ctx.eval_tables(Tu, Td, coef)
+        b0.record(stream)
+        for _ in range(steps):
+            ctx.backward(go)
+        b1.record(stream)
+        stream.synchronize()
+        ms_bwd = b0.elapsed_time(b1) / steps
+    # algorithmic HBM bytes of a step under this decomposition, per spin: the
+    # table read and grad_T written (8 nm each), the ratios R written once
+    # and read twice (CI precontraction gathers, coefficient gradient), the
+    # CI weights C written once and read twice (N sum, table gradient)
+    nm = [s.n_elec[sp] * (s.n_orb[sp] - s.n_elec[sp]) for sp in (0, 1)]
+    U = [int((s.exc[sp].orders() > 0).sum()) + 1 for sp in (0, 1)]
+    step_bytes = float(W) * sum(16 * nm[sp] + 48 * U[sp] for sp in (0, 1)) + 16.0 * s.n_det
     out = dict(value=W * s.n_det / (ms * 1e-3), unit="walker.det/s", ms_per_step=ms,
+               ms_backward=ms_bwd,
                workload=f"water-like, {W} walkers, {s.n_det} determinants, FP64; "
-                        "step = forward from the tables + backward (grad_c, grad_T)")
+                        "step = forward from the tables + backward (grad_c, grad_T)",
+               roofline=roofline_block("adjoint step (eval_tables + backward, all kernels)",
+                                       step_bytes, ms * 1e-3,
+                                       note="bytes: T read and grad_T written, R written once "
+                                            "and read twice, C written once and read twice, "
+                                            "per spin; coef and grad_c"))
     if cpu:
         import oracle
         k = min(W, 256)
@@ -295,15 +448,32 @@ def run_adjoint(steps, warmup, cpu=True):
     return out
 
 
-def run_uneven(steps, warmup, n_moves=4, precision="fp64"):
+def _uneven_one(j, n_moves):
+    return synth_mod().uneven_instances(W=256, n_moves=n_moves, only=[j])[0]
+
+
+def uneven_workloads(n_moves=4, workers=16):
+    """The 64 uneven instances, generated in a process pool (the generator is
+    pure Python per determinant); call before the GPU is touched."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(workers, os.cpu_count() or 1),
+                                mp_context=mp.get_context("fork")) as ex:
+        wls = list(ex.map(_uneven_one, range(64), [n_moves] * 64))
+    log(f"uneven: 64 instances generated in {time.perf_counter() - t0:.1f} s")
+    return wls
+
+
+def run_uneven(steps, warmup, n_moves=4, precision="fp64", wls=None, cpu=True):
     """64 instances of uneven size (n = 5..64 electrons per spin, m = 4n,
     100..200 000 determinants, 256 walkers each) moved together: one step =
     a proposal + commit of one electron in every instance, issued as one
     group launch per walker-tile size (FP64, or the mixed form)."""
     import torch
     from paper_1106_2456_amd import Context, Group
-    log("uneven: generating 64 instances")
-    wls = synth_mod().uneven_instances(W=256, n_moves=n_moves)
+    if wls is None:
+        wls = uneven_workloads(n_moves)
     ctxs = []
     for w in wls:
         sy = w.system
@@ -356,17 +526,57 @@ def run_uneven(steps, warmup, n_moves=4, precision="fp64"):
     ms = e0.elapsed_time(e1) / steps
     wdets = sum(256 * w.system.n_det for w in wls)
     st = torch.stack([o[3] for o in outs]).cpu().numpy()
-    return dict(value=wdets / (ms * 1e-3), unit="walker.det/s", ms_per_step=ms,
-                walker_dets_per_step=wdets, status_bits=int(np.bitwise_or.reduce(st.ravel())),
-                tiles={str(ctxs[idx[0]].get_plan(0)["walker_tile"]): len(idx) for _, idx in groups},
-                workload="64 uneven instances x 256 walkers (n 5..64 per spin, m = 4n, "
-                         f"N_det 1e2..2e5 log-uniform), {precision}; step = one proposal + "
-                         "commit of every instance, one group launch per walker-tile size, eager")
+    # algorithmic bytes of one step's determinant launches (every instance's
+    # moving spin; the average over the timed moves)
+    byts = []
+    for k in range(n_moves):
+        tot = 0.0
+        for w in wls:
+            e = int(w.moves.electron[k])
+            sp = 0 if e < w.system.n_elec[0] else 1
+            n, m = w.system.n_elec[sp], w.system.n_orb[sp] - w.system.n_elec[sp]
+            tot += bytes_per_launch(w.system.exc[sp], 256, n, m, precision, fused=False)
+        byts.append(tot)
+    out = dict(value=wdets / (ms * 1e-3), unit="walker.det/s", ms_per_step=ms,
+               walker_dets_per_step=wdets, status_bits=int(np.bitwise_or.reduce(st.ravel())),
+               tiles={str(ctxs[idx[0]].get_plan(0)["walker_tile"]): len(idx) for _, idx in groups},
+               workload="64 uneven instances x 256 walkers (n 5..64 per spin, m = 4n, "
+                        f"N_det 1e2..2e5 log-uniform), {precision}; step = one proposal + "
+                        "commit of every instance, one group launch per walker-tile size, eager",
+               roofline=roofline_block("group step (all kernels of one proposal + commit)",
+                                       float(np.mean(byts)), ms * 1e-3,
+                                       note="bytes: the determinant launches' algorithmic bytes "
+                                            "of every instance; time: the whole step"))
+    if cpu:
+        out["cpu_baseline"] = uneven_cpu_baseline(wls)
+    return out
+
+
+def uneven_cpu_baseline(wls, n_inst=16):
+    """The oracle on 2 walkers x 1 move of the n_inst instances with the
+    fewest walker.det (the largest ones take minutes per walker)."""
+    import oracle
+    order = np.argsort([w.system.n_det * w.meta["n"] ** 3 for w in wls])[:n_inst]
+    t0 = time.perf_counter()
+    wd = 0
+    for i in order:
+        w = wls[i]
+        e = int(w.moves.electron[0])
+        pos = w.walkers.pos[:2].copy()
+        oracle.move(w.system, pos, e, pos[:, e] + w.moves.disp[0, :2])
+        wd += 2 * w.system.n_det
+    dt = time.perf_counter() - t0
+    return dict(value=wd / dt, unit="walker.det/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"2 walkers x 1 move of the {n_inst} instances with the least work "
+                       f"(full-LU oracle, {dt:.1f} s)")
 
 
 def synth_mod():
     import synth
     return synth
+
+
+ALL_ROWS = "cfg3_fp64,cfg3_mixed,cfg3_mixed_gemm,cfg4_adjoint,cfg5_uneven_fp64,cfg5_uneven_mixed"
 
 
 def main():
@@ -380,9 +590,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--repeat", type=int, default=8,
                     help="back-to-back determinant-kernel launches per HIP event pair")
-    ap.add_argument("--rows", default="",
-                    help="also measure these other rows of the path (comma list of "
-                         "adjoint, uneven, uneven_mixed); reported under 'rows'")
+    ap.add_argument("--rows", default=ALL_ROWS,
+                    help="other rows of the path to measure (comma list of " + ALL_ROWS +
+                         ", cfg3_mixed_gemm_ksum64; empty for none); reported under 'rows'")
+    ap.add_argument("--row-steps", type=int, default=3,
+                    help="timed sweeps of the molecular-shaped rows (64 moves each)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the forms, run a plain device copy (torch.neg, out=) of this many "
                          "MiB three times: the known-size reference for the HBM byte counters")
@@ -392,6 +604,12 @@ def main():
               "independent, so a multi-GPU run would shard them with no per-move "
               "communication; this build measures the one-GPU share.", file=sys.stderr)
         sys.exit(2)
+    rows_wanted = [x for x in args.rows.split(",") if x]
+    for r in rows_wanted:
+        if r not in ALL_ROWS.split(",") + ["cfg3_mixed_gemm_ksum64"]:
+            raise SystemExit(f"unknown row {r!r}")
+    # the uneven instances are generated on the host cores before any GPU work
+    uneven_wls = uneven_workloads() if any(r.startswith("cfg5") for r in rows_wanted) else None
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -408,17 +626,33 @@ def main():
             f"det kernel {r['det_avg_us']:.1f} us ({r['det_gbs']:.0f} GB/s, {r['det_tflops']:.2f} TFLOP/s; "
             f"{r['det_single_us']:.1f} us one launch per event pair) plan {r['plan'][0]}")
         forms[f] = r
+    cpu = None if args.no_cpu else cpu_baseline(wl)
     rows = {}
-    for r in [x for x in args.rows.split(",") if x]:
-        if r == "adjoint":
+    mol = mol_cpu = None
+    for r in rows_wanted:
+        t0 = time.perf_counter()
+        if r.startswith("cfg3_"):
+            if mol is None:
+                mol = molecular_workload()
+            prec = r[len("cfg3_"):]
+            rows[r] = run_molecular(*mol, prec, args.row_steps, 1)
+            if not args.no_cpu:
+                if mol_cpu is None:
+                    mol_cpu = cpu_baseline(mol[0], probe=16, max_moves=1)
+                rows[r]["cpu_baseline"] = mol_cpu
+            torch.cuda.empty_cache()
+        elif r == "cfg4_adjoint":
             rows[r] = run_adjoint(args.steps, args.warmup, cpu=not args.no_cpu)
-        elif r == "uneven":
-            rows[r] = run_uneven(min(args.steps, 10), args.warmup)
-        elif r == "uneven_mixed":
-            rows[r] = run_uneven(min(args.steps, 10), args.warmup, precision="mixed")
-        else:
-            raise SystemExit(f"unknown row {r!r}")
-        log(f"{r}: {rows[r]['ms_per_step']:.3f} ms/step  {rows[r]['value']:.3e} walker.det/s")
+        elif r.startswith("cfg5_uneven_"):
+            prec = r[len("cfg5_uneven_"):]
+            rows[r] = run_uneven(min(args.steps, 10), args.warmup, precision=prec, wls=uneven_wls,
+                                 cpu=not args.no_cpu and r == "cfg5_uneven_fp64")
+            if not args.no_cpu and r != "cfg5_uneven_fp64" and "cfg5_uneven_fp64" in rows:
+                rows[r]["cpu_baseline"] = rows["cfg5_uneven_fp64"]["cpu_baseline"]
+            torch.cuda.empty_cache()
+        rf = rows[r].get("roofline", {})
+        log(f"{r}: {rows[r]['ms_per_step']:.3f} ms/step  {rows[r]['value']:.3e} walker.det/s  "
+            f"roofline {rf.get('frac', float('nan')):.3f} of HBM ({time.perf_counter() - t0:.0f} s)")
     if args.copy_mib > 0:
         x = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
@@ -428,11 +662,10 @@ def main():
         log(f"copy reference: 3 x torch.neg over {args.copy_mib} MiB (read + write each)")
         del x, y
     if not forms:
-        # rows only (e.g. `--forms "" --rows adjoint` under a profiler)
+        # rows only (e.g. `--forms "" --rows cfg4_adjoint` under a profiler)
         print(json.dumps({"rows": rows}))
         return
     head = forms.get("fp64") or next(iter(forms.values()))
-    cpu = None if args.no_cpu else cpu_baseline(wl)
     achieved = head["det_gbs"]
     traffic = measured_traffic(head["plan"]) if head["precision"] == "fp64" else None
     out = {
