@@ -172,6 +172,21 @@ mde_status mde_propose(mde_ctx *ctx, int32_t e, const double *new_orb,
 mde_status mde_grad_lap(mde_ctx *ctx, int32_t e, const double *cur_orb,
                         double *grad, double *lap, int32_t *status);
 
+/* grad_i ln Psi and lap_i Psi / Psi of every electron i at the current
+ * positions (Sec. IV: the laplacian of all particles once per sweep, for
+ * the kinetic energy).  orb_up [W][n_up][5][n_orb_up] and orb_dn hold every
+ * electron's orbital block at its current position (the library keeps
+ * values only).  Outputs grad [W][n_up + n_dn][3] and lap [W][n_up + n_dn]
+ * (device, caller-owned); status bit MDE_ST_NONFINITE marks a walker with a
+ * non-finite output.  Each excitation's derivative is the bordered
+ * determinant of Sec. IV-A read at R; summed with the CI weights the
+ * adjugate terms regroup by table entry into dN/dT_V (the table gradient),
+ * so the call costs one cofactor gather over the excitations per spin plus
+ * two n x n x m products per walker and spin.  FP64 form only
+ * (MDE_UNSUPPORTED otherwise); leaves any pending proposal in place. */
+mde_status mde_local_derivs(mde_ctx *ctx, const double *orb_up, const double *orb_dn,
+                            double *grad, double *lap, int32_t *status);
+
 /* Commit the pending proposal of electron e for walkers with accept[w] != 0
  * (uint8 [W]): Sherman-Morrison update of A0^-1 (Sec. III SM eq.), table,
  * reference determinant and CI sum.  Every refresh_every calls the state is

@@ -205,6 +205,22 @@ class Context:
                   "grad_lap")
         return out
 
+    def local_derivs(self, orb_up: torch.Tensor, orb_dn: torch.Tensor, out=None):
+        """grad_i ln Psi [W, n_tot, 3] and lap_i Psi / Psi [W, n_tot] of every
+        electron at the current positions; orb_* are every electron's blocks
+        (as for init).  Returns (grad, lap, status)."""
+        W = self.W
+        _check_dev(orb_up, torch.float64, (W, self.n_elec[0], 5, self.n_orb[0]), "orb_up")
+        _check_dev(orb_dn, torch.float64, (W, self.n_elec[1], 5, self.n_orb[1]), "orb_dn")
+        nt = self.n_elec[0] + self.n_elec[1]
+        if out is None:
+            out = (self._empty((W, nt, 3)), self._empty((W, nt)),
+                   torch.zeros(W, dtype=torch.int32, device=self.device))
+        g, l, st = out
+        self._chk(lib().mde_local_derivs(self._h, _ptr(orb_up), _ptr(orb_dn), _ptr(g), _ptr(l),
+                                         _ptr(st)), "local_derivs")
+        return out
+
     def accept(self, e: int, mask: torch.Tensor):
         _check_dev(mask, torch.uint8, (self.W,), "accept mask")
         self.state_seq += 1

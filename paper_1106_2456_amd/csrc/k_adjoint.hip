@@ -109,9 +109,18 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
     const int wl = tid % WT, slot = tid / WT, nslot = nthr / WT;
     extern __shared__ double tabs[];
     const int nm = n * m;
-    for (int idx = tid; idx < nm * WT; idx += nthr) {
-        const int ee = idx % nm, l = idx / nm, w = t * WT + l;
-        tabs[ee * WTP + l] = (w < W) ? Tin[(size_t)w * nm + ee] : 0.0;
+    if (Tin) {
+        for (int idx = tid; idx < nm * WT; idx += nthr) {
+            const int ee = idx % nm, l = idx / nm, w = t * WT + l;
+            tabs[ee * WTP + l] = (w < W) ? Tin[(size_t)w * nm + ee] : 0.0;
+        }
+    } else {
+        // the context's own table, walker-tiled [tile][entry][WT]
+        const auto Tt = MDE_G(double, S.T) + (size_t)t * nm * WT;
+        for (int idx = tid; idx < nm * WT; idx += nthr) {
+            const int ee = idx / WT, l = idx % WT, w = t * WT + l;
+            tabs[ee * WTP + l] = (w < W) ? Tt[idx] : 0.0;
+        }
     }
     __syncthreads();
     const int w = t * WT + wl;
@@ -174,18 +183,23 @@ hipError_t launch_backward(hipStream_t st, const InstDev *d_inst, const InstDev 
     double *gT[2] = {grad_T_up, grad_T_dn};
     for (int s = 0; s < 2; ++s) {
         if (!gT[s]) continue;
-        const SpinDev &S = h.s[s];
-        const size_t lds = sizeof(double) * (size_t)S.n * S.m * S.WTP;
-        if (S.n * S.m > 65535) return hipErrorInvalidValue;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_grad_T,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, S.n * S.m), dim3(256), lds, st, d_inst, s,
-                           Tin[s], gT[s]);
-        e = hipGetLastError();
+        e = launch_grad_T(st, d_inst, h, s, Tin[s], gT[s]);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
+                         const double *Tin, double *grad_T) {
+    const SpinDev &S = h.s[spin];
+    const size_t lds = sizeof(double) * (size_t)S.n * S.m * S.WTP;
+    if (S.n * S.m > 65535 || lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_grad_T,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, S.n * S.m), dim3(256), lds, st, d_inst, spin, Tin,
+                       grad_T);
+    return hipGetLastError();
 }
 
 }  // namespace mde

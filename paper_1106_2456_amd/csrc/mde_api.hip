@@ -704,6 +704,7 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
     h.st = cv.take<int32_t>(W);
     h.counter = cv.take<int32_t>(64);
     h.Lnew = cv.take<double>(W);
+    h.gz = prec == 0 ? cv.take<double>((size_t)W * nmax * mmax) : nullptr;
     if (base) {
         c->d_inst = d_inst;
         h.W = W;
@@ -1358,6 +1359,37 @@ mde_status mde_accept(mde_ctx *c, int32_t e, const uint8_t *accept) {
     c->accept_count++;
     if (c->d.refresh_every > 0 && c->accept_count % c->d.refresh_every == 0)
         return full_eval(c, nullptr, nullptr, nullptr, nullptr, nullptr, c->d.precision != 0);
+    return MDE_OK;
+}
+
+mde_status mde_local_derivs(mde_ctx *c, const double *orb_up, const double *orb_dn, double *grad,
+                            double *lap, int32_t *status) {
+    if (!c) return MDE_INVALID;
+    if (!c->initialized || c->adjoint_state) MDE_FAIL(c, MDE_STATE, "call mde_init first");
+    if (c->d.precision != MDE_FP64)
+        MDE_FAIL(c, MDE_UNSUPPORTED, "all-electron derivatives are computed in the FP64 form");
+    if (!orb_up || !orb_dn || !grad || !lap) MDE_FAIL(c, MDE_INVALID, "orbital blocks and outputs required");
+    for (int s = 0; s < 2; ++s) {
+        if (local_derivs_lds(c->sp[s].n, c->sp[s].m) > 160 * 1024 ||
+            sizeof(double) * (size_t)c->sp[s].n * c->sp[s].m * lds_row_stride(c->WT) > 160 * 1024)
+            MDE_FAIL(c, MDE_UNSUPPORTED, "spin %d: tables too large for the derivative kernels", s);
+    }
+    // ratios of both spins and the CI weights of both spins at the current positions
+    for (int s = 0; s < 2; ++s)
+        if (!c->R_valid[s]) {
+            mde_status st = run_values(c, s);
+            if (st) return st;
+        }
+    for (int s = 0; s < 2; ++s) {
+        mde_status st = ensure_C(c, s);
+        if (st) return st;
+    }
+    MDE_HIP(c, launch_inv_nold(c->stream, c->d_inst, c->h));
+    const double *orb[2] = {orb_up, orb_dn};
+    for (int s = 0; s < 2; ++s) {
+        MDE_HIP(c, launch_grad_T(c->stream, c->d_inst, c->h, s, nullptr, c->h.gz));
+        MDE_HIP(c, launch_local_derivs(c->stream, c->d_inst, c->h, s, orb[s], grad, lap, status));
+    }
     return MDE_OK;
 }
 

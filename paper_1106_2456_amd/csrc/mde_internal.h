@@ -125,6 +125,7 @@ struct InstDev {
     int32_t *st;     // [W] internal status bits
     int32_t *counter;  // work-queue counter of the persistent kernel
     double *Lnew;    // [W] adjoint scratch: go / N per walker
+    double *gz;      // [W][nmax * mmax] table gradient dN/dT / N of one spin (all-electron derivatives)
 };
 
 // Per-call move arguments (device array for groups, by value otherwise).
@@ -236,6 +237,15 @@ hipError_t launch_backward(hipStream_t st, const InstDev *d_inst, const InstDev 
                            const double *go, const double *Nw, const double *coef,
                            double *grad_coef, double *grad_T_up, double *grad_T_dn,
                            const double *T_up, const double *T_dn);
+// table gradient of one spin, grad_T[w] = Lnew[w] dN/dT_V[w] ([W][n][m]);
+// Tin NULL: the context's own (walker-tiled) table
+hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
+                         const double *Tin, double *grad_T);
+// all-electron derivatives (k_local.hip): Lnew = 1 / N, then per spin from gz
+hipError_t launch_inv_nold(hipStream_t st, const InstDev *d_inst, const InstDev &h);
+size_t local_derivs_lds(int n, int m);
+hipError_t launch_local_derivs(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
+                               const double *orb, double *grad, double *lap, int32_t *status);
 hipError_t launch_eval_finish(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
                               double *log_abs, double *sign, int32_t *status);
 hipError_t launch_sgauss(hipStream_t st, int nb, const double *centres, const double *expo,
