@@ -32,7 +32,7 @@ __global__ void k_inv_nold(const InstDev *__restrict__ insts) {
 
 // One block per walker, ceil(n / 16) waves; wave v owns rows i in
 // [16v, 16v + 16) of M.  v_mfma_f64_16x16x4f64 lanes: A[l % 16][l / 16],
-// B[l / 16][l % 16], D[4 (l / 16) + j][l % 16].
+// B[l / 16][l % 16], and element j of the result D[l / 16 + 4 j][l % 16].
 __global__ void __launch_bounds__(256)
 k_local_derivs(const InstDev *__restrict__ insts, int spin, const double *__restrict__ orb,
                const double *__restrict__ Yn, double *__restrict__ grad, double *__restrict__ lap,
@@ -63,7 +63,7 @@ k_local_derivs(const InstDev *__restrict__ insts, int spin, const double *__rest
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) Z[(4 * lk + j) * zs + pt + lr] = acc[j];
+        for (int j = 0; j < 4; ++j) Z[(lk + 4 * j) * zs + pt + lr] = acc[j];
     }
     __syncthreads();
     // K[i][r] = sum_p Z[i][p] T_V[r][p]
@@ -77,7 +77,7 @@ k_local_derivs(const InstDev *__restrict__ insts, int spin, const double *__rest
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) K[(4 * lk + j) * ks + rt + lr] = acc[j];
+        for (int j = 0; j < 4; ++j) K[(lk + 4 * j) * ks + rt + lr] = acc[j];
     }
     __syncthreads();
     // lane (row i = i0 + l % 16, component a = l / 16): the row contraction

@@ -340,45 +340,55 @@ hipError_t launch_refresh_small(hipStream_t st, const InstDev *d_inst, const Ins
 }
 
 // ---------------------------------------------------------------------------
-// table GEMM in FP64: T_V[w] = A^-1[w] Phi_V[w], one block per walker,
-// 64-column chunks of Phi_V staged in LDS.  In MIXED mode the FP32 table is
+// table GEMM in FP64 on the matrix cores: T_V[w] = A^-1[w] Phi_V[w] (Sec. III
+// table; Sec. V: one matrix product instead of dot products), one block of
+// four waves per walker, A^-1 staged in LDS, 16 x 16 output tiles of
+// v_mfma_f64_16x16x4f64 (lanes: A[l % 16][l / 16], B[l / 16][l % 16], result
+// element j at [l / 16 + 4 j][l % 16]).  In the FP32-table forms the table is
 // the rounded FP64 product at a refresh.
 // ---------------------------------------------------------------------------
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256)
 k_table_gemm(const InstDev *__restrict__ insts, int spin) {
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[spin];
     const int w = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int n = S.n, m = S.m, no = S.no;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int n = S.n, m = S.m, no = S.no, WT = S.WT;
     extern __shared__ double sh[];
-    double *Bs = sh;              // n*n
-    double *Pv = sh + n * n;      // n*64
+    double *Bs = sh;              // n x n
     for (int idx = tid; idx < n * n; idx += 256) Bs[idx] = S.B[(size_t)w * n * n + idx];
-    for (int c0 = 0; c0 < m; c0 += 64) {
-        __syncthreads();
-        for (int idx = tid; idx < n * 64; idx += 256) {
-            const int k = idx >> 6, pp = idx & 63;
-            Pv[idx] = (c0 + pp < m) ? S.Phi[((size_t)w * n + k) * no + n + c0 + pp] : 0.0;
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    const int RT = (n + 15) >> 4, PT = (m + 15) >> 4;
+    const auto Pv = MDE_G(double, S.Phi) + (size_t)w * n * no + n;     // Phi_V[k][p] at k * no + p
+    const size_t tb = (size_t)(w / WT) * n * m * WT + (w % WT);
+    for (int t = wave; t < RT * PT; t += 4) {
+        const int rt = (t / PT) * 16, pt = (t % PT) * 16;
+        const int r = rt + lr, p = pt + lr;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < n; k0 += 4) {
+            const int k = k0 + lk;
+            const double a = (r < n && k < n) ? Bs[r * n + k] : 0.0;
+            const double b = (k < n && p < m) ? Pv[(size_t)k * no + p] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
-        __syncthreads();
-        for (int idx = tid; idx < n * 64; idx += 256) {
-            const int r = idx >> 6, pp = idx & 63;
-            if (c0 + pp >= m) continue;
-            double s = 0.0;
-            for (int k = 0; k < n; ++k) s = fma(Bs[r * n + k], Pv[k * 64 + pp], s);
-            const int WT = S.WT;
-            const size_t o = (((size_t)(w / WT) * n + r) * m + c0 + pp) * WT + (w % WT);
-            if (I.prec == 0) S.T[o] = s;
-            else S.T32[o] = (float)s;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int rr = rt + lk + 4 * j;
+            if (rr >= n || p >= m) continue;
+            const size_t o = tb + (size_t)(rr * m + p) * WT;
+            if (I.prec == 0) S.T[o] = acc[j];
+            else S.T32[o] = (float)acc[j];
         }
     }
 }
 
 hipError_t launch_table_gemm(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin) {
     const int n = h.s[spin].n;
-    const size_t lds = sizeof(double) * (n * n + n * 64);
+    const size_t lds = sizeof(double) * (size_t)n * n;
     hipLaunchKernelGGL(k_table_gemm, dim3(h.W), dim3(256), lds, st, d_inst, spin);
     return hipGetLastError();
 }
