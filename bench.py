@@ -440,12 +440,73 @@ def run_adjoint(steps, warmup, cpu=True):
         k = min(W, 256)
         tu, td = Tu[:k].cpu().numpy(), Td[:k].cpu().numpy()
         t0 = time.perf_counter()
-        oracle.tables(s, tu, td)
+        reps = 0
+        while time.perf_counter() - t0 < 8.0:
+            oracle.tables(s, tu, td)
+            reps += 1
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = dict(value=k * s.n_det / dt, unit="walker.det/s",
+        out["cpu_baseline"] = dict(value=reps * k * s.n_det / dt, unit="walker.det/s",
                                    cores=oracle.num_threads(), kind="oracle",
-                                   sample=f"{k} walkers, forward + adjoint by full LU ({dt:.2f} s)")
+                                   sample=f"{k} walkers x {reps}, forward + adjoint by full LU "
+                                          f"({dt:.1f} s)")
     return out
+
+
+def run_local(wl, steps, cpu=True, tag="water-like"):
+    """All-electron gradients and laplacians at fixed positions (one call of
+    mde_local_derivs: every electron of every walker), FP64."""
+    import torch
+    s = wl.system
+    W = wl.walkers.W
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = build_context(wl, "fp64", stream, refresh_every=None)
+        pos = torch.as_tensor(wl.walkers.pos, device="cuda")
+        nu = s.n_elec[0]
+        ou = ctx.sgauss_eval(0, pos[:, :nu].contiguous())
+        od = ctx.sgauss_eval(1, pos[:, nu:].contiguous())
+        ctx.init(ou, od)
+        out = ctx.local_derivs(ou, od)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.local_derivs(ou, od, out=out)
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    n_tot = sum(s.n_elec)
+    # algorithmic bytes per call and spin: the CI weights (8 U), the table read
+    # twice (8 nm each), dN/dT written and read (16 nm), the inverse (8 n^2),
+    # every electron's four derivative rows (32 n (n + m)), outputs (32 n)
+    byts = 0.0
+    for sp in (0, 1):
+        n, m = s.n_elec[sp], s.n_orb[sp] - s.n_elec[sp]
+        U = int((s.exc[sp].orders() > 0).sum()) + 1
+        byts += W * (8 * U + 32 * n * m + 8 * n * n + 32 * n * (n + m) + 32 * n)
+    row = dict(value=W * s.n_det * n_tot / (ms * 1e-3), unit="walker.det.electron/s",
+               ms_per_step=ms,
+               workload=f"{tag}: all-electron grad ln Psi and lap Psi/Psi at fixed positions, "
+                        f"{W} walkers, {s.n_det} determinants, {n_tot} electrons, FP64; "
+                        "step = one call for every electron of every walker",
+               roofline=roofline_block("local derivatives (table gradient + MFMA products, all kernels)",
+                                       byts, ms * 1e-3))
+    if cpu:
+        import oracle
+        k = min(W, 64)
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 8.0:
+            for e in range(n_tot):
+                oracle.grad_lap(s, wl.walkers.pos[:k], e)
+            reps += 1
+        dt = time.perf_counter() - t0
+        row["cpu_baseline"] = dict(value=reps * k * s.n_det * n_tot / dt, unit="walker.det.electron/s",
+                                   cores=oracle.num_threads(), kind="oracle",
+                                   sample=f"{k} walkers x every electron x {reps} (row-replaced full "
+                                          f"LUs, {dt:.1f} s)")
+    return row
 
 
 def _uneven_one(j, n_moves):
@@ -556,18 +617,24 @@ def uneven_cpu_baseline(wls, n_inst=16):
     """The oracle on 2 walkers x 1 move of the n_inst instances with the
     fewest walker.det (the largest ones take minutes per walker)."""
     import oracle
-    order = np.argsort([w.system.n_det * w.meta["n"] ** 3 for w in wls])[:n_inst]
+    order = np.argsort([w.system.n_det * w.meta["n"] ** 3 for w in wls])
     t0 = time.perf_counter()
     wd = 0
+    done = 0
+    # instances in order of increasing work, 16 walkers x 1 move each, until
+    # about 8 s of host time
     for i in order:
         w = wls[i]
         e = int(w.moves.electron[0])
-        pos = w.walkers.pos[:2].copy()
-        oracle.move(w.system, pos, e, pos[:, e] + w.moves.disp[0, :2])
-        wd += 2 * w.system.n_det
+        pos = w.walkers.pos[:16].copy()
+        oracle.move(w.system, pos, e, pos[:, e] + w.moves.disp[0, :16])
+        wd += 16 * w.system.n_det
+        done += 1
+        if time.perf_counter() - t0 > 8.0:
+            break
     dt = time.perf_counter() - t0
     return dict(value=wd / dt, unit="walker.det/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"2 walkers x 1 move of the {n_inst} instances with the least work "
+                sample=f"16 walkers x 1 move of the {done} instances with the least work "
                        f"(full-LU oracle, {dt:.1f} s)")
 
 
@@ -576,7 +643,8 @@ def synth_mod():
     return synth
 
 
-ALL_ROWS = "cfg3_fp64,cfg3_mixed,cfg3_mixed_gemm,cfg4_adjoint,cfg5_uneven_fp64,cfg5_uneven_mixed"
+ALL_ROWS = ("cfg3_fp64,cfg3_mixed,cfg3_mixed_gemm,cfg4_adjoint,cfg5_uneven_fp64,cfg5_uneven_mixed,"
+            "local_cfg2,local_cfg3")
 
 
 def main():
@@ -638,8 +706,15 @@ def main():
             rows[r] = run_molecular(*mol, prec, args.row_steps, 1)
             if not args.no_cpu:
                 if mol_cpu is None:
-                    mol_cpu = cpu_baseline(mol[0], probe=16, max_moves=1)
+                    mol_cpu = cpu_baseline(mol[0], probe=128, max_moves=1)
                 rows[r]["cpu_baseline"] = mol_cpu
+            torch.cuda.empty_cache()
+        elif r == "local_cfg2":
+            rows[r] = run_local(wl, args.steps, cpu=not args.no_cpu)
+        elif r == "local_cfg3":
+            if mol is None:
+                mol = molecular_workload()
+            rows[r] = run_local(mol[0], 5, cpu=not args.no_cpu, tag="molecular-shaped")
             torch.cuda.empty_cache()
         elif r == "cfg4_adjoint":
             rows[r] = run_adjoint(args.steps, args.warmup, cpu=not args.no_cpu)
