@@ -82,6 +82,10 @@ typedef enum {
 #define MDE_ST_SMALL_RATIO  2   /* |det A'/det A| below 1e-300 or not finite  */
 #define MDE_ST_NONFINITE    4   /* non-finite input or output                 */
 #define MDE_ST_ZERO_PSI     8   /* multi-determinant sum exactly zero / NaN   */
+#define MDE_ST_REF_ILLCOND 16   /* |Psi / (D0_up D0_dn)| > 1e8: the reference
+                                   determinant is near-singular where Psi is
+                                   not (Sec. V); switch the reference
+                                   (mde_set_reference) for this walker       */
 
 /* Limits of this build. */
 #define MDE_MAX_ELEC  64        /* electrons per spin                         */
@@ -130,6 +134,23 @@ mde_status mde_set_excitations(mde_ctx *ctx, int32_t spin, int32_t n_exc,
  * to the lists given to mde_set_excitations (call that first). */
 mde_status mde_set_ci(mde_ctx *ctx, int64_t n_det, const double *coef,
                       const int32_t *up_idx, const int32_t *dn_idx);
+
+/* Reference switching (Sec. V: when the reference matrix is near-singular
+ * while Psi is not, another determinant of the expansion serves as the
+ * reference).  Makes the determinant with up excitation ref_up and down
+ * excitation ref_dn (indices into the lists given to mde_set_excitations)
+ * the reference of this context: its occupied orbitals become orbitals
+ * 0..n-1 of the internal order, every excitation is rewritten relative to it
+ * (its order can grow by the order of the new reference; MDE_UNSUPPORTED
+ * above desc.max_order) and the sign of each determinant's column
+ * reordering is folded into its coefficient, so Psi is unchanged.  Call
+ * after mde_set_ci and before mde_bind_workspace; (0, 0) restores the
+ * caller's reference.  Inputs keep the caller's orbital order (the library
+ * permutes them); outputs of init/propose/grad_lap/local_derivs are the same
+ * quantities; mde_export returns the rebased frame (ratios to the new
+ * reference, its inverse, table and log|det|).  Contexts with a switched
+ * reference cannot join a group (MDE_UNSUPPORTED). */
+mde_status mde_set_reference(mde_ctx *ctx, int32_t ref_up, int32_t ref_dn);
 
 /* ---- workspace --------------------------------------------------------- */
 

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libmde.so")
 MDE_OK, MDE_INVALID, MDE_NOMEM, MDE_DEVICE, MDE_STATE, MDE_UNSUPPORTED = range(6)
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "STATE", 5: "UNSUPPORTED"}
 MDE_FP64, MDE_MIXED, MDE_MIXED_GEMM, MDE_MIXED_GEMM_KSUM64 = 0, 1, 2, 3
-ST_SINGULAR_REF, ST_SMALL_RATIO, ST_NONFINITE, ST_ZERO_PSI = 1, 2, 4, 8
+ST_SINGULAR_REF, ST_SMALL_RATIO, ST_NONFINITE, ST_ZERO_PSI, ST_REF_ILLCOND = 1, 2, 4, 8, 16
 
 
 class MdeDesc(C.Structure):
@@ -41,6 +41,7 @@ _SIGS = {
     "mde_destroy": ([_P], C.c_int),
     "mde_set_excitations": ([_P, _I, _I, _P, _P, _P], C.c_int),
     "mde_set_ci": ([_P, C.c_int64, _P, _P, _P], C.c_int),
+    "mde_set_reference": ([_P, _I, _I], C.c_int),
     "mde_workspace_bytes": ([_P, _I, C.POINTER(C.c_size_t)], C.c_int),
     "mde_bind_workspace": ([_P, _I, _P, C.c_size_t], C.c_int),
     "mde_init": ([_P, _P, _P, _P, _P, _P], C.c_int),

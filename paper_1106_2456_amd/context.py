@@ -135,6 +135,11 @@ class Context:
                   "set_ci")
         self.n_det = int(c.shape[0])
 
+    def set_reference(self, ref_up: int, ref_dn: int):
+        """Switch the reference to the determinant (ref_up, ref_dn) of the
+        caller's excitation lists (before bind)."""
+        self._chk(lib().mde_set_reference(self._h, int(ref_up), int(ref_dn)), "set_reference")
+
     def set_basis(self, spin: int, centres, expo, mo):
         cc = np.ascontiguousarray(centres, np.float64)
         ee = np.ascontiguousarray(expo, np.float64)

@@ -1444,6 +1444,8 @@ __global__ void k_nsum(const InstDev *__restrict__ insts, double *log_abs_psi, d
     I.Nold[w] = s;
     int bits = I.st[w];
     if (!(s != 0.0) || !isfinite(s)) bits |= 8;
+    // the reference determinant carries less than 1e-8 of Psi
+    if (fabs(s) > REF_ILLCOND_N) bits |= 16;
     I.st[w] = bits;
     double la = log(fabs(s));
     double sg = (s > 0.0) ? 1.0 : (s < 0.0 ? -1.0 : 0.0);
@@ -1504,6 +1506,7 @@ __device__ __forceinline__ void finish_walker_v(const InstDev &I, const MoveArgs
     }
     int bits = st & 2;
     if (!(rNp != 0.0) || !isfinite(rNp)) bits |= 8;
+    if (fabs(I.Nnew[w]) > REF_ILLCOND_N) bits |= 16;
     if (!isfinite(ratio) || !isfinite(d[0]) || !isfinite(d[1]) || !isfinite(d[2]) || !isfinite(d[3]))
         bits |= 4;
     if (mv.ratio) mv.ratio[w] = ratio;

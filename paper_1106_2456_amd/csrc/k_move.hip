@@ -1146,6 +1146,24 @@ hipError_t launch_set_moves(hipStream_t st, MoveArgs *d_moves, const MoveArgs *h
     return hipSuccess;
 }
 
+// dst[r][q] = src[r][perm[q]] over rows of no orbital values
+__global__ void k_permute_orbitals(const double *__restrict__ src, double *__restrict__ dst,
+                                   size_t total, int no, const int32_t *__restrict__ perm) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const size_t r = i / no;
+    const int q = (int)(i - r * no);
+    dst[i] = src[r * no + perm[q]];
+}
+
+hipError_t launch_permute_orbitals(hipStream_t st, const double *src, double *dst, int rows, int no,
+                                   const int32_t *perm) {
+    const size_t total = (size_t)rows * no;
+    hipLaunchKernelGGL(k_permute_orbitals, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       src, dst, total, no, perm);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_counter(hipStream_t st, int32_t *counter) {
     return launch_fill_i32(st, counter, 0, 16);
 }

@@ -120,6 +120,19 @@ struct mde_ctx {
     // bumped whenever the work layout is re-established (apply_plan): a group
     // built over this context holds the generation it copied
     long plan_gen = 0;
+    // the caller's expansion as given (kept so that the reference can be
+    // switched, always relative to it)
+    std::vector<int> u_off[2], u_h[2], u_p[2];
+    std::vector<double> u_coef;
+    std::vector<int> u_up, u_dn;
+    bool in_rebase = false;
+    // reference switching: internal orbital q of spin s is the caller's
+    // orbital orb_perm[s][q]; empty = identity
+    std::vector<int32_t> orb_perm[2];
+    int32_t *d_orb_perm[2] = {nullptr, nullptr};
+    double *d_orbx = nullptr;     // [W][5][n_orb] permuted proposal block
+    double *d_orbfull = nullptr;  // [W][n][5][n_orb] up block, then the down block
+    int ref_user[2] = {0, 0};
 };
 
 // default plan for W walkers, keeping the fields the caller set
@@ -705,6 +718,20 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
     h.counter = cv.take<int32_t>(64);
     h.Lnew = cv.take<double>(W);
     h.gz = prec == 0 ? cv.take<double>((size_t)W * nmax * mmax) : nullptr;
+    // reference switching: orbital permutations and the permuted input blocks
+    const bool rebased = !c->orb_perm[0].empty() || !c->orb_perm[1].empty();
+    int32_t *op[2] = {nullptr, nullptr};
+    double *ox = nullptr, *of = nullptr;
+    if (rebased) {
+        for (int s = 0; s < 2; ++s) op[s] = cv.take<int32_t>(c->sp[s].no);
+        ox = cv.take<double>((size_t)W * 5 * nomax);
+        of = cv.take<double>((size_t)W * (c->sp[0].n * c->sp[0].no + c->sp[1].n * c->sp[1].no) * 5);
+    }
+    if (base) {
+        for (int s = 0; s < 2; ++s) c->d_orb_perm[s] = c->orb_perm[s].empty() ? nullptr : op[s];
+        c->d_orbx = ox;
+        c->d_orbfull = of;
+    }
     if (base) {
         c->d_inst = d_inst;
         h.W = W;
@@ -881,6 +908,18 @@ static mde_status full_eval(mde_ctx *c, const double *orb_up, const double *orb_
 }
 
 static void prof_free(mde_ctx *c);
+
+// The caller's orbital blocks in the internal orbital order of a context
+// whose reference was switched (rows of n_orb values, permuted in place of
+// the caller's buffer into the context's scratch); unchanged otherwise.
+static const double *internal_orbitals(mde_ctx *c, int s, const double *orb, int rows,
+                                       double *scratch) {
+    if (!orb || !c->d_orb_perm[s]) return orb;
+    if (launch_permute_orbitals(c->stream, orb, scratch, rows, c->sp[s].no, c->d_orb_perm[s]) !=
+        hipSuccess)
+        return nullptr;
+    return scratch;
+}
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -1068,6 +1107,13 @@ mde_status mde_set_excitations(mde_ctx *c, int32_t spin, int32_t n_exc, const in
     if (n_exc >= (1 << 21)) MDE_FAIL(c, MDE_UNSUPPORTED, "too many excitations");
     sp.have = true;
     c->have_ci = false;
+    if (!c->in_rebase) {
+        c->u_off[spin].assign(offsets, offsets + sp.n_user + 1);
+        c->u_h[spin].assign(holes, holes + offsets[sp.n_user]);
+        c->u_p[spin].assign(particles, particles + offsets[sp.n_user]);
+        c->orb_perm[spin].clear();
+        c->ref_user[spin] = 0;
+    }
     return MDE_OK;
 }
 
@@ -1150,8 +1196,113 @@ mde_status mde_set_ci(mde_ctx *c, int64_t n_det, const double *coef, const int32
         if (sp.chunks.empty()) { sp.chunks.push_back(0); sp.chunks.push_back(0); }
     }
     c->have_ci = true;
+    if (!c->in_rebase) {
+        c->u_coef.assign(coef, coef + n_det);
+        c->u_up.assign(up_idx, up_idx + n_det);
+        c->u_dn.assign(dn_idx, dn_idx + n_det);
+    }
     apply_default_plan(c, c->d.max_walkers);
     return MDE_OK;
+}
+
+// Reference switching (Sec. V: a near-singular reference matrix is handled by
+// taking another determinant of the expansion as the reference).  The
+// determinant with up excitation ref[0] and down excitation ref[1] of the
+// caller's lists becomes the reference: per spin the orbitals are relabelled
+// so that its columns, in their column order, are orbitals 0..n-1 and the
+// others follow in ascending order; every excitation is rewritten relative
+// to the new occupation (holes: new reference orbitals it lacks; particles:
+// its orbitals outside the new reference; both ascending, paired in order),
+// and the sign of the column permutation between the two forms of each
+// determinant is folded into its CI coefficient, so Psi is unchanged.  The
+// orders grow by at most the order of the new reference.
+static mde_status rebase_expansion(mde_ctx *c, const int32_t ref[2]) {
+    std::vector<int> offs[2], hs[2], ps[2], newidx[2];
+    std::vector<double> sgn[2];
+    for (int s = 0; s < 2; ++s) {
+        const int n = c->sp[s].n, no = c->sp[s].no;
+        const std::vector<int> &O = c->u_off[s], &H = c->u_h[s], &P = c->u_p[s];
+        const int nu = (int)O.size() - 1;
+        if (ref[s] < 0 || ref[s] >= nu) MDE_FAIL(c, MDE_INVALID, "reference excitation out of range");
+        auto cols = [&](int u, std::vector<int> &col) {
+            col.resize(n);
+            for (int j = 0; j < n; ++j) col[j] = j;
+            for (int t = O[u]; t < O[u + 1]; ++t) col[H[t]] = P[t];
+        };
+        std::vector<int> cref, perm(no), inv(no, -1);
+        cols(ref[s], cref);
+        std::vector<char> inref(no, 0);
+        for (int j = 0; j < n; ++j) { perm[j] = cref[j]; inref[cref[j]] = 1; }
+        int q = n;
+        for (int o = 0; o < no; ++o)
+            if (!inref[o]) perm[q++] = o;
+        for (int k = 0; k < no; ++k) inv[perm[k]] = k;
+        c->orb_perm[s] = std::vector<int32_t>(perm.begin(), perm.end());
+        // new index: ref <-> 0 swapped, the rest unchanged
+        newidx[s].resize(nu);
+        for (int u = 0; u < nu; ++u) newidx[s][u] = u;
+        newidx[s][ref[s]] = 0;
+        newidx[s][0] = ref[s];
+        std::vector<std::vector<int>> nh(nu), np_(nu);
+        sgn[s].assign(nu, 1.0);
+        std::vector<int> col, in_u(no);
+        for (int u = 0; u < nu; ++u) {
+            cols(u, col);
+            std::fill(in_u.begin(), in_u.end(), 0);
+            for (int j = 0; j < n; ++j) in_u[col[j]] = 1;
+            std::vector<int> h2, p2;
+            for (int j = 0; j < n; ++j)
+                if (!in_u[perm[j]]) h2.push_back(j);
+            for (int j = 0; j < n; ++j)
+                if (inv[col[j]] >= n) p2.push_back(inv[col[j]]);
+            std::sort(p2.begin(), p2.end());
+            if ((int)h2.size() > c->d.max_order)
+                MDE_FAIL(c, MDE_UNSUPPORTED, "excitation %d has order %zu relative to the new reference "
+                         "(max_order %d)", u, h2.size(), c->d.max_order);
+            // caller's orbitals of the new-frame column list, and the parity
+            // of the permutation to the caller's column list
+            std::vector<int> a(n);
+            for (int j = 0; j < n; ++j) a[j] = perm[j];
+            for (size_t t = 0; t < h2.size(); ++t) a[h2[t]] = perm[p2[t]];
+            std::vector<int> where(no, -1), pm(n);
+            for (int j = 0; j < n; ++j) where[a[j]] = j;
+            for (int j = 0; j < n; ++j) pm[j] = where[col[j]];
+            int inv_count = 0;
+            for (int i = 0; i < n; ++i)
+                for (int j = i + 1; j < n; ++j) inv_count += pm[i] > pm[j];
+            sgn[s][u] = (inv_count & 1) ? -1.0 : 1.0;
+            nh[newidx[s][u]] = h2;
+            np_[newidx[s][u]] = p2;
+        }
+        offs[s].assign(1, 0);
+        for (int u = 0; u < nu; ++u) {
+            hs[s].insert(hs[s].end(), nh[u].begin(), nh[u].end());
+            ps[s].insert(ps[s].end(), np_[u].begin(), np_[u].end());
+            offs[s].push_back((int)hs[s].size());
+        }
+    }
+    const int64_t nd = (int64_t)c->u_coef.size();
+    std::vector<double> coef(nd);
+    std::vector<int> up(nd), dn(nd);
+    for (int64_t I = 0; I < nd; ++I) {
+        coef[I] = c->u_coef[I] * sgn[0][c->u_up[I]] * sgn[1][c->u_dn[I]];
+        up[I] = newidx[0][c->u_up[I]];
+        dn[I] = newidx[1][c->u_dn[I]];
+    }
+    c->in_rebase = true;
+    mde_status st = MDE_OK;
+    for (int s = 0; s < 2 && st == MDE_OK; ++s)
+        st = mde_set_excitations(c, s, (int)offs[s].size() - 1, offs[s].data(), hs[s].data(),
+                                 ps[s].data());
+    if (st == MDE_OK) st = mde_set_ci(c, nd, coef.data(), up.data(), dn.data());
+    c->in_rebase = false;
+    if (st == MDE_OK) {
+        c->ref_user[0] = ref[0];
+        c->ref_user[1] = ref[1];
+        if (ref[0] == 0) c->orb_perm[0].clear();
+        if (ref[1] == 0) c->orb_perm[1].clear();
+    }
+    return st;
 }
 
 mde_status mde_sgauss_set_basis(mde_ctx *c, int32_t spin, int32_t nb, const double *centres,
@@ -1230,6 +1381,9 @@ mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
                                  sizeof(int) * sp.inv_ent.size(), hipMemcpyHostToDevice));
         MDE_HIP(c, hipMemcpy(c->d_perm_user[s], sp.iperm.data(), sizeof(int) * sp.U,
                              hipMemcpyHostToDevice));
+        if (c->d_orb_perm[s])
+            MDE_HIP(c, hipMemcpy(c->d_orb_perm[s], c->orb_perm[s].data(), sizeof(int32_t) * sp.no,
+                                 hipMemcpyHostToDevice));
         if (c->nb[s] > 0) {
             MDE_HIP(c, hipMemcpy(c->d_centres[s], c->centres[s].data(),
                                  sizeof(double) * c->centres[s].size(), hipMemcpyHostToDevice));
@@ -1258,7 +1412,20 @@ mde_status mde_init(mde_ctx *c, const double *orb_up, const double *orb_dn, doub
     if (!orb_up || !orb_dn) MDE_FAIL(c, MDE_INVALID, "orbital blocks required");
     MDE_HIP(c, launch_fill_i32(c->stream, c->h.st, 0, c->W));
     c->accept_count = 0;
-    return full_eval(c, orb_up, orb_dn, log_abs_psi, sign_psi, status);
+    const double *ou = internal_orbitals(c, 0, orb_up, c->W * c->sp[0].n * 5, c->d_orbfull);
+    const double *od = internal_orbitals(
+        c, 1, orb_dn, c->W * c->sp[1].n * 5,
+        c->d_orbfull ? c->d_orbfull + (size_t)c->W * c->sp[0].n * 5 * c->sp[0].no : nullptr);
+    if (!ou || !od) MDE_FAIL(c, MDE_DEVICE, "orbital permutation launch failed");
+    return full_eval(c, ou, od, log_abs_psi, sign_psi, status);
+}
+
+mde_status mde_set_reference(mde_ctx *c, int32_t ref_up, int32_t ref_dn) {
+    if (!c) return MDE_INVALID;
+    if (c->bound) MDE_FAIL(c, MDE_STATE, "the reference is fixed once the workspace is bound");
+    if (!c->have_ci || c->u_coef.empty()) MDE_FAIL(c, MDE_STATE, "set excitations and CI first");
+    const int32_t ref[2] = {ref_up, ref_dn};
+    return rebase_expansion(c, ref);
 }
 
 mde_status mde_refresh(mde_ctx *c, double *log_abs_psi, double *sign_psi, int32_t *status) {
@@ -1277,6 +1444,8 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
     const int s = spin_of(c, e, &row);
     mde_status st = ensure_C(c, s);
     if (st) return st;
+    orb = internal_orbitals(c, s, orb, c->W * 5, c->d_orbx);
+    if (!orb) MDE_FAIL(c, MDE_DEVICE, "orbital permutation launch failed");
     MoveArgs m{};
     m.e = e;
     m.spin = s;
@@ -1387,8 +1556,10 @@ mde_status mde_local_derivs(mde_ctx *c, const double *orb_up, const double *orb_
     MDE_HIP(c, launch_inv_nold(c->stream, c->d_inst, c->h));
     const double *orb[2] = {orb_up, orb_dn};
     for (int s = 0; s < 2; ++s) {
+        const double *o = internal_orbitals(c, s, orb[s], c->W * c->sp[s].n * 5, c->d_orbfull);
+        if (!o) MDE_FAIL(c, MDE_DEVICE, "orbital permutation launch failed");
         MDE_HIP(c, launch_grad_T(c->stream, c->d_inst, c->h, s, nullptr, c->h.gz));
-        MDE_HIP(c, launch_local_derivs(c->stream, c->d_inst, c->h, s, orb[s], grad, lap, status));
+        MDE_HIP(c, launch_local_derivs(c->stream, c->d_inst, c->h, s, o, grad, lap, status));
     }
     return MDE_OK;
 }
@@ -1832,6 +2003,7 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
         if (!ctxs[i] || !ctxs[i]->bound) return MDE_STATE;
         if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->d.precision != ctxs[0]->d.precision)
             return MDE_INVALID;
+        if (ctxs[i]->d_orb_perm[0] || ctxs[i]->d_orb_perm[1]) return MDE_UNSUPPORTED;
     }
     size_t need = 0;
     if (mde_group_workspace_bytes(ctxs, n, &need) != MDE_OK || bytes < need) return MDE_NOMEM;

@@ -10,6 +10,9 @@ constexpr int MAXN = 64;     // electrons per spin
 constexpr int MAXM = 256;    // virtual orbitals per spin
 constexpr int MAXK = 8;      // excitation order
 constexpr int NSUM = 6;      // sums over excitations: N, q-term, x, y, z, laplacian
+// |Psi / (D0_up D0_dn)| above which a walker's reference determinant is
+// flagged as near-singular (status bit 16: switch the reference)
+constexpr double REF_ILLCOND_N = 1e8;
 
 // One unit of determinant work: excitations [u0, u1) of spin `spin` for the
 // walkers of tile `tile` of instance `inst`.  Results go to partial-sum slot
@@ -252,6 +255,9 @@ hipError_t launch_sgauss(hipStream_t st, int nb, const double *centres, const do
                          int n_orb, const double *mo, int npos, const double *pos,
                          double *out);
 hipError_t launch_reset_counter(hipStream_t st, int32_t *counter);
+// dst[r][q] = src[r][perm[q]] for rows x no values (reference switching)
+hipError_t launch_permute_orbitals(hipStream_t st, const double *src, double *dst, int rows, int no,
+                                   const int32_t *perm);
 // copy n per-instance move arguments (host array) to d_moves, as kernel
 // arguments (no host buffer is read when the copy runs)
 hipError_t launch_set_moves(hipStream_t st, MoveArgs *d_moves, const MoveArgs *h_moves, int n);
