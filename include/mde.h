@@ -208,6 +208,19 @@ mde_status mde_grad_lap(mde_ctx *ctx, int32_t e, const double *cur_orb,
 mde_status mde_local_derivs(mde_ctx *ctx, const double *orb_up, const double *orb_dn,
                             double *grad, double *lap, int32_t *status);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation and outputs as mde_local_derivs, with its per-call
+ * intermediate (the table gradient of one spin, W x n x m doubles) held in
+ * a fixed device array of the library (32 MiB, 4 194 304 doubles, kept by
+ * every GPU the library runs on until the process ends) instead of the
+ * context's workspace.  The call itself allocates nothing.  MDE_UNSUPPORTED
+ * when W x n x m of a spin exceeds that size.  All calls on one GPU share
+ * the array: calls that overlap in time on one GPU (on different streams or
+ * threads) race. */
+mde_status mde_local_derivs_noalloc(mde_ctx *ctx, const double *orb_up, const double *orb_dn,
+                                    double *grad, double *lap, int32_t *status);
+
 /* Commit the pending proposal of electron e for walkers with accept[w] != 0
  * (uint8 [W]): Sherman-Morrison update of A0^-1 (Sec. III SM eq.), table,
  * reference determinant and CI sum.  Every refresh_every calls the state is

@@ -18,6 +18,8 @@
 // (occupied columns, then virtual).  Per walker and spin this is two dense
 // products of n x n x m, run on v_mfma_f64_16x16x4f64, and four row
 // contractions; the per-excitation work is the cofactor gather of Y.
+#include <mutex>
+
 #include "mde_internal.h"
 
 namespace mde {
@@ -100,7 +102,8 @@ size_t local_derivs_lds(int n, int m) {
 }
 
 hipError_t launch_local_derivs(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
-                               const double *orb, double *grad, double *lap, int32_t *status) {
+                               const double *orb, const double *Yn, double *grad, double *lap,
+                               int32_t *status) {
     const SpinDev &S = h.s[spin];
     const int waves = (S.n + 15) / 16;
     const size_t lds = local_derivs_lds(S.n, S.m);
@@ -109,8 +112,38 @@ hipError_t launch_local_derivs(hipStream_t st, const InstDev *d_inst, const Inst
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int n_tot = h.s[0].n + h.s[1].n;
     hipLaunchKernelGGL(k_local_derivs, dim3(h.W), dim3(64 * waves), lds, st, d_inst, spin, orb,
-                       h.gz, grad, lap, status, spin == 0 ? 0 : h.s[0].n, n_tot);
+                       Yn, grad, lap, status, spin == 0 ? 0 : h.s[0].n, n_tot);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free variant of the all-electron derivatives: the
+// table gradient dN/dT / N of one spin ([W][n][m] doubles), held in a
+// file-scope device array that every GPU the library runs on keeps until the
+// process ends.  Host code never passes the array's name to a kernel: the
+// per-device address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+static __device__ __align__(256) double scratch[LOCAL_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+double *scratch_addr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t local_scratch(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_addr[dev] = static_cast<double *>(p);
+    }
+    *out = scratch_addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_inv_nold(hipStream_t st, const InstDev *d_inst, const InstDev &h) {

@@ -1531,8 +1531,8 @@ mde_status mde_accept(mde_ctx *c, int32_t e, const uint8_t *accept) {
     return MDE_OK;
 }
 
-mde_status mde_local_derivs(mde_ctx *c, const double *orb_up, const double *orb_dn, double *grad,
-                            double *lap, int32_t *status) {
+static mde_status local_derivs(mde_ctx *c, const double *orb_up, const double *orb_dn,
+                               double *grad, double *lap, int32_t *status, bool no_alloc) {
     if (!c) return MDE_INVALID;
     if (!c->initialized || c->adjoint_state) MDE_FAIL(c, MDE_STATE, "call mde_init first");
     if (c->d.precision != MDE_FP64)
@@ -1553,15 +1553,34 @@ mde_status mde_local_derivs(mde_ctx *c, const double *orb_up, const double *orb_
         mde_status st = ensure_C(c, s);
         if (st) return st;
     }
+    double *yz = c->h.gz;
+    if (no_alloc) {
+        for (int s = 0; s < 2; ++s)
+            if ((size_t)c->W * c->sp[s].n * c->sp[s].m > LOCAL_SCRATCH_DOUBLES)
+                MDE_FAIL(c, MDE_UNSUPPORTED,
+                         "W x n x m = %zu exceeds the %zu doubles of the allocation-free scratch",
+                         (size_t)c->W * c->sp[s].n * c->sp[s].m, LOCAL_SCRATCH_DOUBLES);
+        MDE_HIP(c, local_scratch(&yz));
+    }
     MDE_HIP(c, launch_inv_nold(c->stream, c->d_inst, c->h));
     const double *orb[2] = {orb_up, orb_dn};
     for (int s = 0; s < 2; ++s) {
         const double *o = internal_orbitals(c, s, orb[s], c->W * c->sp[s].n * 5, c->d_orbfull);
         if (!o) MDE_FAIL(c, MDE_DEVICE, "orbital permutation launch failed");
-        MDE_HIP(c, launch_grad_T(c->stream, c->d_inst, c->h, s, nullptr, c->h.gz));
-        MDE_HIP(c, launch_local_derivs(c->stream, c->d_inst, c->h, s, o, grad, lap, status));
+        MDE_HIP(c, launch_grad_T(c->stream, c->d_inst, c->h, s, nullptr, yz));
+        MDE_HIP(c, launch_local_derivs(c->stream, c->d_inst, c->h, s, o, yz, grad, lap, status));
     }
     return MDE_OK;
+}
+
+mde_status mde_local_derivs(mde_ctx *c, const double *orb_up, const double *orb_dn, double *grad,
+                            double *lap, int32_t *status) {
+    return local_derivs(c, orb_up, orb_dn, grad, lap, status, false);
+}
+
+mde_status mde_local_derivs_noalloc(mde_ctx *c, const double *orb_up, const double *orb_dn,
+                                    double *grad, double *lap, int32_t *status) {
+    return local_derivs(c, orb_up, orb_dn, grad, lap, status, true);
 }
 
 mde_status mde_export(mde_ctx *c, int32_t what, int32_t spin, double *dst) {

@@ -248,7 +248,12 @@ hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h
 hipError_t launch_inv_nold(hipStream_t st, const InstDev *d_inst, const InstDev &h);
 size_t local_derivs_lds(int n, int m);
 hipError_t launch_local_derivs(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
-                               const double *orb, double *grad, double *lap, int32_t *status);
+                               const double *orb, const double *Yn, double *grad, double *lap,
+                               int32_t *status);
+// the allocation-free variant's scratch: a device array of this many doubles
+// (32 MiB), its address on the current device
+constexpr size_t LOCAL_SCRATCH_DOUBLES = (size_t)4 << 20;
+hipError_t local_scratch(double **out);
 hipError_t launch_eval_finish(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
                               double *log_abs, double *sign, int32_t *status);
 hipError_t launch_sgauss(hipStream_t st, int nb, const double *centres, const double *expo,
