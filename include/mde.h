@@ -231,6 +231,24 @@ mde_status mde_local_derivs_noalloc(mde_ctx *ctx, const double *orb_up, const do
  * next proposal or export needs them. */
 mde_status mde_accept(mde_ctx *ctx, int32_t e, const uint8_t *accept);
 
+/* Metropolis loop with drift, entirely on the device (Sec. II sampling of
+ * |Psi|^2 by single-electron moves; the gradient evaluated at R for the
+ * drift and at R' for the reverse move, "twice per step").  n_steps sweeps;
+ * in each, electrons 0..n_up+n_dn-1 in order: g = grad_e ln Psi(R) (as
+ * mde_grad_lap), r' = r_e + tau g + sqrt(tau) chi, ratio and g' at R' (as
+ * mde_propose), accepted when u < |ratio|^2 G(r <- r') / G(r' <- r) with
+ * G(b <- a) = exp(-|b - a - tau g(a)|^2 / (2 tau)), then committed (as
+ * mde_accept).  Orbitals come from the s-Gaussian provider (set its basis
+ * for both spins; MDE_STATE otherwise).  Random numbers are inputs:
+ * normals [n_steps][n_up+n_dn][W][3] (chi) and uniforms
+ * [n_steps][n_up+n_dn][W] (u), device.  pos [W][n_up+n_dn][3] (device,
+ * in/out) holds the walkers' positions and must match the state of the last
+ * mde_init; accepted [W] (int32, in/out) counts accepted moves.  No host
+ * synchronisation: the loop can be captured into a graph (its host-side
+ * refresh cadence is fixed at capture). */
+mde_status mde_vmc(mde_ctx *ctx, int32_t n_steps, double tau, const double *normals,
+                   const double *uniforms, double *pos, int32_t *accepted, int32_t *status);
+
 /* Copy internal state for checks.  what: 0 = A0^-1 of spin s [W][n][n],
  * 1 = table T_V of spin s [W][n][m] (FP64; in MIXED mode converted from
  * FP32), 2 = excited ratios D_u/D_0 of spin s [W][n_exc] in the caller's

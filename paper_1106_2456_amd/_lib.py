@@ -51,6 +51,7 @@ _SIGS = {
     "mde_accept": ([_P, _I, _P], C.c_int),
     "mde_local_derivs": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "mde_local_derivs_noalloc": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "mde_vmc": ([_P, _I, C.c_double, _P, _P, _P, _P, _P], C.c_int),
     "mde_export": ([_P, _I, _I, _P], C.c_int),
     "mde_eval_tables": ([_P, _P, _P, _P, _P, _P, _P], C.c_int),
     "mde_backward": ([_P, _P, _P, _P, _P], C.c_int),

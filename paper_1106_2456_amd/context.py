@@ -226,6 +226,23 @@ class Context:
                                          _ptr(st)), "local_derivs")
         return out
 
+    def vmc(self, n_steps: int, tau: float, normals: torch.Tensor, uniforms: torch.Tensor,
+            pos: torch.Tensor, accepted: torch.Tensor, status=None):
+        """n_steps Metropolis sweeps with drift on the device; pos [W, n_tot, 3]
+        and accepted [W] (int32) are updated in place.  normals
+        [n_steps, n_tot, W, 3] and uniforms [n_steps, n_tot, W] are the
+        random inputs."""
+        W, nt = self.W, self.n_elec[0] + self.n_elec[1]
+        _check_dev(normals, torch.float64, (n_steps, nt, W, 3), "normals")
+        _check_dev(uniforms, torch.float64, (n_steps, nt, W), "uniforms")
+        _check_dev(pos, torch.float64, (W, nt, 3), "pos")
+        _check_dev(accepted, torch.int32, (W,), "accepted")
+        st = status if status is not None else torch.zeros(W, dtype=torch.int32, device=self.device)
+        self.state_seq += 1
+        self._chk(lib().mde_vmc(self._h, int(n_steps), float(tau), _ptr(normals), _ptr(uniforms),
+                                _ptr(pos), _ptr(accepted), _ptr(st)), "vmc")
+        return st
+
     def accept(self, e: int, mask: torch.Tensor):
         _check_dev(mask, torch.uint8, (self.W,), "accept mask")
         self.state_seq += 1

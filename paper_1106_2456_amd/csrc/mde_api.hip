@@ -130,6 +130,8 @@ struct mde_ctx {
     // orbital orb_perm[s][q]; empty = identity
     std::vector<int32_t> orb_perm[2];
     int32_t *d_orb_perm[2] = {nullptr, nullptr};
+    double *d_vmc = nullptr;      // Metropolis loop scratch (see mde_vmc)
+    uint8_t *d_vmc_mask = nullptr;
     double *d_orbx = nullptr;     // [W][5][n_orb] permuted proposal block
     double *d_orbfull = nullptr;  // [W][n][5][n_orb] up block, then the down block
     int ref_user[2] = {0, 0};
@@ -727,7 +729,13 @@ static size_t carve(mde_ctx *c, int W, char *base, size_t *max_items_out = nullp
         ox = cv.take<double>((size_t)W * 5 * nomax);
         of = cv.take<double>((size_t)W * (c->sp[0].n * c->sp[0].no + c->sp[1].n * c->sp[1].no) * 5);
     }
+    // Metropolis loop: cur, new positions, g(R), g(R') [W][3] each; ratio,
+    // two laplacians [W]; two orbital blocks [W][5][nomax]; the accept mask
+    double *vm = cv.take<double>((size_t)W * (15 + 10 * (size_t)nomax));
+    uint8_t *vmask = cv.take<uint8_t>(W);
     if (base) {
+        c->d_vmc = vm;
+        c->d_vmc_mask = vmask;
         for (int s = 0; s < 2; ++s) c->d_orb_perm[s] = c->orb_perm[s].empty() ? nullptr : op[s];
         c->d_orbx = ox;
         c->d_orbfull = of;
@@ -1581,6 +1589,46 @@ mde_status mde_local_derivs(mde_ctx *c, const double *orb_up, const double *orb_
 mde_status mde_local_derivs_noalloc(mde_ctx *c, const double *orb_up, const double *orb_dn,
                                     double *grad, double *lap, int32_t *status) {
     return local_derivs(c, orb_up, orb_dn, grad, lap, status, true);
+}
+
+mde_status mde_vmc(mde_ctx *c, int32_t n_steps, double tau, const double *normals,
+                   const double *uniforms, double *pos, int32_t *accepted, int32_t *status) {
+    if (!c) return MDE_INVALID;
+    if (!c->initialized || c->adjoint_state) MDE_FAIL(c, MDE_STATE, "call mde_init first");
+    if (c->nb[0] <= 0 || c->nb[1] <= 0)
+        MDE_FAIL(c, MDE_STATE, "the loop evaluates orbitals with the s-Gaussian provider: set its basis");
+    if (n_steps < 0 || !(tau > 0.0)) MDE_FAIL(c, MDE_INVALID, "need n_steps >= 0 and tau > 0");
+    if (n_steps > 0 && (!normals || !uniforms || !pos || !accepted))
+        MDE_FAIL(c, MDE_INVALID, "random inputs, positions and the acceptance counts are required");
+    const int W = c->W, n_tot = c->d.n_elec[0] + c->d.n_elec[1];
+    const int nomax = c->h.nomax;
+    double *cur = c->d_vmc, *newp = cur + (size_t)W * 3, *g0 = newp + (size_t)W * 3;
+    double *g1 = g0 + (size_t)W * 3, *ratio = g1 + (size_t)W * 3, *lap0 = ratio + W;
+    double *lap1 = lap0 + W, *blk0 = lap1 + W, *blk1 = blk0 + (size_t)W * 5 * nomax;
+    for (int step = 0; step < n_steps; ++step)
+        for (int e = 0; e < n_tot; ++e) {
+            int row;
+            const int s = spin_of(c, e, &row);
+            const size_t mv = (size_t)step * n_tot + e;
+            // grad_e ln Psi at the current position (the drift)
+            MDE_HIP(c, launch_vmc_drift(c->stream, W, n_tot, e, tau, pos, g0, nullptr, cur, newp, 0));
+            MDE_HIP(c, launch_sgauss(c->stream, c->nb[s], c->d_centres[s], c->d_expo[s], c->sp[s].no,
+                                     c->d_mo[s], W, cur, blk0));
+            mde_status st = do_propose(c, e, blk0, nullptr, g0, lap0, status);
+            if (st) return st;
+            // the proposal and its ratio and gradient at R'
+            MDE_HIP(c, launch_vmc_drift(c->stream, W, n_tot, e, tau, pos, g0, normals + mv * W * 3,
+                                        cur, newp, 1));
+            MDE_HIP(c, launch_sgauss(c->stream, c->nb[s], c->d_centres[s], c->d_expo[s], c->sp[s].no,
+                                     c->d_mo[s], W, newp, blk1));
+            st = do_propose(c, e, blk1, ratio, g1, lap1, status);
+            if (st) return st;
+            MDE_HIP(c, launch_vmc_decide(c->stream, W, n_tot, e, tau, pos, cur, newp, g0, g1, ratio,
+                                         uniforms + mv * W, c->d_vmc_mask, accepted));
+            st = mde_accept(c, e, c->d_vmc_mask);
+            if (st) return st;
+        }
+    return MDE_OK;
 }
 
 mde_status mde_export(mde_ctx *c, int32_t what, int32_t spin, double *dst) {

@@ -254,6 +254,13 @@ hipError_t launch_local_derivs(hipStream_t st, const InstDev *d_inst, const Inst
 // (32 MiB), its address on the current device
 constexpr size_t LOCAL_SCRATCH_DOUBLES = (size_t)4 << 20;
 hipError_t local_scratch(double **out);
+// Metropolis loop with drift (k_vmc.hip); phase 0 copies electron e's
+// position to cur, phase 1 forms the proposal newp
+hipError_t launch_vmc_drift(hipStream_t st, int W, int n_tot, int e, double tau, const double *pos,
+                            const double *g0, const double *chi, double *cur, double *newp, int phase);
+hipError_t launch_vmc_decide(hipStream_t st, int W, int n_tot, int e, double tau, double *pos,
+                             const double *cur, const double *newp, const double *g0, const double *g1,
+                             const double *ratio, const double *u, uint8_t *mask, int32_t *accepted);
 hipError_t launch_eval_finish(hipStream_t st, const InstDev *d_inst, const InstDev &h_inst,
                               double *log_abs, double *sign, int32_t *status);
 hipError_t launch_sgauss(hipStream_t st, int nb, const double *centres, const double *expo,
