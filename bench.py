@@ -494,18 +494,19 @@ def run_local(wl, steps, cpu=True, tag="water-like"):
                                        byts, ms * 1e-3))
     if cpu:
         import oracle
-        k = min(W, 64)
+        k = min(W, 64 if max(s.n_elec) <= 8 else 16)
         t0 = time.perf_counter()
-        reps = 0
+        done = 0
+        # electrons one at a time (each one is a full pass of row-replaced
+        # LUs over every determinant) until about 8 s of host time
         while time.perf_counter() - t0 < 8.0:
-            for e in range(n_tot):
-                oracle.grad_lap(s, wl.walkers.pos[:k], e)
-            reps += 1
+            oracle.grad_lap(s, wl.walkers.pos[:k], done % n_tot)
+            done += 1
         dt = time.perf_counter() - t0
-        row["cpu_baseline"] = dict(value=reps * k * s.n_det * n_tot / dt, unit="walker.det.electron/s",
+        row["cpu_baseline"] = dict(value=k * s.n_det * done / dt, unit="walker.det.electron/s",
                                    cores=oracle.num_threads(), kind="oracle",
-                                   sample=f"{k} walkers x every electron x {reps} (row-replaced full "
-                                          f"LUs, {dt:.1f} s)")
+                                   sample=f"{k} walkers x {done} electrons (row-replaced full LUs, "
+                                          f"{dt:.1f} s)")
     return row
 
 
@@ -699,6 +700,7 @@ def main():
     mol = mol_cpu = None
     for r in rows_wanted:
         t0 = time.perf_counter()
+        log(f"{r}: starting")
         if r.startswith("cfg3_"):
             if mol is None:
                 mol = molecular_workload()
