@@ -8,6 +8,8 @@
 // u) and cof(S)[j][l] = d det S / d S[j][l].  The table-entry gradient is
 // gathered through an inverted index (entry -> (u, j, l)), so every output
 // element is one fixed-order sum: no atomics, bitwise-reproducible.
+#include <algorithm>
+
 #include "mde_internal.h"
 #include "smalldet.h"
 
@@ -94,17 +96,18 @@ __device__ double cof_entry_generic(const double *tabs, const uint4 &ex, int k, 
     return y[l];
 }
 
-// grad_T_sigma: block (walker tile, table entry); the tile's table in LDS;
-// the block's waves (lanes over walkers) take contiguous pieces of the
-// entry's inverted list, and their sums are added in wave order.
+// grad_T_sigma: block (walker tile, part) stages the tile's table in LDS once
+// and takes the part's contiguous range of table entries; each entry's
+// inverted list is summed by one walker lane of one slot (lanes of a slot
+// are the tile's walkers), in list order, so every output element is one
+// fixed-order sum.
 __global__ void __launch_bounds__(256)
 k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__ Tin,
-         double *__restrict__ grad_T) {
-    __shared__ double red[256];
+         double *__restrict__ grad_T, int parts) {
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[spin];
     const int n = S.n, m = S.m, WT = S.WT, WTP = S.WTP, W = I.W;
-    const int t = blockIdx.x, e = blockIdx.y;
+    const int t = blockIdx.x, part = blockIdx.y;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int wl = tid % WT, slot = tid / WT, nslot = nthr / WT;
     extern __shared__ double tabs[];
@@ -124,42 +127,43 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
     }
     __syncthreads();
     const int w = t * WT + wl;
-    const double *__restrict__ Cb = S.C + (size_t)t * S.U * WT;
-    const int a = S.inv_off[e], b = S.inv_off[e + 1];
-    const int per = (b - a + nslot - 1) / nslot;
-    const int qa = a + slot * per, qb = min(b, qa + per);
-    double acc = 0.0;
-    // the next list entry, its record and its CI weight are loaded while the
-    // current cofactor is formed
-    int code_n = qa < qb ? S.inv_ent[qa] : 0;
-    uint4 ex_n = qa < qb ? S.ex[code_n >> 10] : make_uint4(0, 0, 0, 0);
-    double cw_n = qa < qb ? Cb[(size_t)(code_n >> 10) * WT + wl] : 0.0;
-    for (int q = qa; q < qb; ++q) {
-        const int code = code_n;
-        const uint4 ex = ex_n;
-        const double cw = cw_n;
-        if (q + 1 < qb) {
-            code_n = S.inv_ent[q + 1];
-            ex_n = S.ex[code_n >> 10];
-            cw_n = Cb[(size_t)(code_n >> 10) * WT + wl];
+    if (w >= W) return;
+    const double gw = I.Lnew[w];
+    const auto Cb = MDE_G(double, S.C) + (size_t)t * S.U * WT + wl;
+    const auto inv_off = MDE_G(int32_t, S.inv_off);
+    const auto inv_ent = MDE_G(int32_t, S.inv_ent);
+    const uint4 *__restrict__ exs = S.ex;
+    const int per = (nm + parts - 1) / parts;
+    const int e_begin = part * per, e_end = min(nm, e_begin + per);
+    for (int e = e_begin + slot; e < e_end; e += nslot) {
+        const int a = inv_off[e], b = inv_off[e + 1];
+        double acc = 0.0;
+        // the next list entry, its record and its CI weight are loaded while
+        // the current cofactor is formed
+        int code_n = a < b ? inv_ent[a] : 0;
+        uint4 ex_n = a < b ? exs[code_n >> 10] : make_uint4(0, 0, 0, 0);
+        double cw_n = a < b ? Cb[(size_t)(code_n >> 10) * WT] : 0.0;
+        for (int q = a; q < b; ++q) {
+            const int code = code_n;
+            const uint4 ex = ex_n;
+            const double cw = cw_n;
+            if (q + 1 < b) {
+                code_n = inv_ent[q + 1];
+                ex_n = exs[code_n >> 10];
+                cw_n = Cb[(size_t)(code_n >> 10) * WT];
+            }
+            const int k = (code >> 6) & 15, j = (code >> 3) & 7, l = code & 7;
+            double cf;
+            switch (k) {
+                case 1: cf = 1.0; break;
+                case 2: cf = cof_entry<2>(tabs, ex, m, WTP, wl, j, l); break;
+                case 3: cf = cof_entry<3>(tabs, ex, m, WTP, wl, j, l); break;
+                case 4: cf = cof_entry<4>(tabs, ex, m, WTP, wl, j, l); break;
+                default: cf = cof_entry_generic(tabs, ex, k, m, WTP, wl, j, l); break;
+            }
+            acc = fma(cw, cf, acc);
         }
-        const int k = (code >> 6) & 15, j = (code >> 3) & 7, l = code & 7;
-        double cf;
-        switch (k) {
-            case 1: cf = 1.0; break;
-            case 2: cf = cof_entry<2>(tabs, ex, m, WTP, wl, j, l); break;
-            case 3: cf = cof_entry<3>(tabs, ex, m, WTP, wl, j, l); break;
-            case 4: cf = cof_entry<4>(tabs, ex, m, WTP, wl, j, l); break;
-            default: cf = cof_entry_generic(tabs, ex, k, m, WTP, wl, j, l); break;
-        }
-        acc = fma(cw, cf, acc);
-    }
-    red[slot * WT + wl] = acc;
-    __syncthreads();
-    if (slot == 0 && w < W) {
-        double sum = 0.0;
-        for (int v = 0; v < nslot; ++v) sum += red[v * WT + wl];
-        grad_T[(size_t)w * nm + e] = I.Lnew[w] * sum;
+        grad_T[(size_t)w * nm + e] = gw * acc;
     }
 }
 
@@ -197,8 +201,11 @@ hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)k_grad_T,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, S.n * S.m), dim3(256), lds, st, d_inst, spin, Tin,
-                       grad_T);
+    // parts per tile: enough blocks to cover the chip about four times over
+    const int nm = S.n * S.m;
+    const int parts = std::max(1, std::min(std::max(nm / 16, 1), (1024 + S.n_tiles - 1) / S.n_tiles));
+    hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, parts), dim3(256), lds, st, d_inst, spin, Tin,
+                       grad_T, parts);
     return hipGetLastError();
 }
 
