@@ -97,10 +97,12 @@ __device__ double cof_entry_generic(const double *tabs, const uint4 &ex, int k, 
 }
 
 // grad_T_sigma: block (walker tile, part) stages the tile's table in LDS once
-// and takes the part's contiguous range of table entries; each entry's
-// inverted list is summed by one walker lane of one slot (lanes of a slot
-// are the tile's walkers), in list order, so every output element is one
-// fixed-order sum.
+// and takes the part's contiguous range of table entries.  With one entry
+// per part (wide tiles: few tiles, short tables) the entry's inverted list
+// is split over the block's slots (lanes of a slot are the tile's walkers)
+// and the slot sums are added in slot order; otherwise each entry's list is
+// summed by one lane of one slot in list order.  Either way every output
+// element is one fixed-order sum.
 __global__ void __launch_bounds__(256)
 k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__ Tin,
          double *__restrict__ grad_T, int parts) {
@@ -127,16 +129,24 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
     }
     __syncthreads();
     const int w = t * WT + wl;
-    if (w >= W) return;
-    const double gw = I.Lnew[w];
+    // (walkers past W compute on zero tables and store nothing: every
+    // thread reaches the block barrier of the split form)
+    const bool live = w < W;
+    const double gw = live ? I.Lnew[w] : 0.0;
     const auto Cb = MDE_G(double, S.C) + (size_t)t * S.U * WT + wl;
     const auto inv_off = MDE_G(int32_t, S.inv_off);
     const auto inv_ent = MDE_G(int32_t, S.inv_ent);
     const uint4 *__restrict__ exs = S.ex;
+    const bool split = parts == nm;
     const int per = (nm + parts - 1) / parts;
     const int e_begin = part * per, e_end = min(nm, e_begin + per);
-    for (int e = e_begin + slot; e < e_end; e += nslot) {
-        const int a = inv_off[e], b = inv_off[e + 1];
+    for (int e = e_begin + (split ? 0 : slot); e < e_end; e += (split ? 1 : nslot)) {
+        int a = inv_off[e], b = inv_off[e + 1];
+        if (split) {
+            const int pl = (b - a + nslot - 1) / nslot;
+            a = min(b, a + slot * pl);
+            b = min(b, a + pl);
+        }
         double acc = 0.0;
         // the next list entry, its record and its CI weight are loaded while
         // the current cofactor is formed
@@ -163,7 +173,18 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
             }
             acc = fma(cw, cf, acc);
         }
-        grad_T[(size_t)w * nm + e] = gw * acc;
+        if (!split) {
+            if (live) grad_T[(size_t)w * nm + e] = gw * acc;
+            continue;
+        }
+        __shared__ double red[256];
+        red[slot * WT + wl] = acc;
+        __syncthreads();
+        if (slot == 0 && live) {
+            double sum = 0.0;
+            for (int v = 0; v < nslot; ++v) sum += red[v * WT + wl];
+            grad_T[(size_t)w * nm + e] = gw * sum;
+        }
     }
 }
 
@@ -201,9 +222,13 @@ hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)k_grad_T,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    // parts per tile: enough blocks to cover the chip about four times over
+    // parts per tile: one entry per block (its list split over the block's
+    // slots) while that stays within 2^16 blocks, else enough ranges of
+    // entries to cover the chip about four times over
     const int nm = S.n * S.m;
-    const int parts = std::max(1, std::min(std::max(nm / 16, 1), (1024 + S.n_tiles - 1) / S.n_tiles));
+    const int parts = (size_t)S.n_tiles * nm <= 65536
+                          ? nm
+                          : std::max(1, std::min(std::max(nm / 16, 1), (1024 + S.n_tiles - 1) / S.n_tiles));
     hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, parts), dim3(256), lds, st, d_inst, spin, Tin,
                        grad_T, parts);
     return hipGetLastError();
