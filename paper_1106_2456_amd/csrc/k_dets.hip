@@ -110,31 +110,49 @@ __device__ double det_one_generic(int k, const uint4 &ex, const TT *__restrict__
 }
 
 // Loop over the item's excitations (slot-strided; records [u0, u1) read from
-// global memory); the CI weight of the next excitation is loaded while the
-// current one is evaluated.
+// global memory).  The records and CI weights of the next DP excitations of
+// the lane are loaded while the current ones are evaluated (a ring of DP
+// register sets, indexed statically by unrolling the loop DP-fold), so the
+// lane waits on a global load once per DP excitations at most.
 template <int K, typename TT, int MODE, int WT>
 __device__ __forceinline__ void det_loop(const WorkItem &it, const SpinDev &S,
                                          const uint4 *__restrict__ recs, const TT *tabs,
                                          const TT *gs, const TT *cs, int wl, int slot, int nslot,
                                          double acc[NSUM]) {
+    constexpr int DP = 4;
     const int len = it.u1 - it.u0;
     const size_t base = ((size_t)it.tile * S.U + it.u0) * WT;
     const auto Cb = MDE_G(double, S.C) + base;
     const auto Rb = MDE_GW(double, S.R) + base;
+    const uint4 *__restrict__ rg = recs;
     const int m = S.m, WTP = S.WTP;
-    int j = slot;
-    double Cn = 0.0;
-    if (MODE == DM_PROPOSE && j < len) Cn = Cb[(size_t)j * WT + wl];
-    for (; j < len; j += nslot) {
-        const uint4 ex = recs[j];
-        const double Cu = Cn;
-        if (MODE == DM_PROPOSE && j + nslot < len) Cn = Cb[(size_t)(j + nslot) * WT + wl];
-        double R;
-        if (K > 0)
-            R = det_one<(K > 0 ? K : 1), TT, MODE>(ex, tabs, gs, cs, m, WTP, wl, Cu, acc);
-        else
-            R = det_one_generic<TT, MODE>(it.order, ex, tabs, gs, cs, m, WTP, wl, Cu, acc);
-        if (MODE == DM_VALUES) Rb[(size_t)j * WT + wl] = R;
+    uint4 exr[DP];
+    double cr[DP];
+#pragma unroll
+    for (int i = 0; i < DP; ++i) {
+        const int j = slot + i * nslot;
+        exr[i] = j < len ? rg[j] : make_uint4(0, 0, 0, 0);
+        cr[i] = (MODE == DM_PROPOSE && j < len) ? Cb[(size_t)j * WT + wl] : 0.0;
+    }
+    for (int j0 = slot; j0 < len; j0 += DP * nslot) {
+#pragma unroll
+        for (int i = 0; i < DP; ++i) {
+            const int j = j0 + i * nslot;
+            if (j >= len) break;
+            const uint4 ex = exr[i];
+            const double Cu = cr[i];
+            const int jn = j + DP * nslot;
+            if (jn < len) {
+                exr[i] = rg[jn];
+                if (MODE == DM_PROPOSE) cr[i] = Cb[(size_t)jn * WT + wl];
+            }
+            double R;
+            if (K > 0)
+                R = det_one<(K > 0 ? K : 1), TT, MODE>(ex, tabs, gs, cs, m, WTP, wl, Cu, acc);
+            else
+                R = det_one_generic<TT, MODE>(it.order, ex, tabs, gs, cs, m, WTP, wl, Cu, acc);
+            if (MODE == DM_VALUES) Rb[(size_t)j * WT + wl] = R;
+        }
     }
 }
 
@@ -808,7 +826,7 @@ __device__ __forceinline__ void item64_fused_end(const WorkItem &it, const InstD
 // At the end the block sums W over the waves, contracts it with e^b (the
 // values are loaded before the barrier) and writes the item's NSUM sums per
 // walker in a fixed order.
-template <typename TT, int MODE>
+template <typename TT, int MODE, bool GEN>
 __device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, const SpinDev &S,
                                        const MoveArgs &mv, uint4 *exl, unsigned char *tab_raw,
                                        const int32_t *__restrict__ bounds, int tid, int nthr,
@@ -897,7 +915,10 @@ __device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, con
                 case 2: det_runs64<2, TT, MODE>(S, it.tile, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
                 case 3: det_direct64<3, TT, MODE>(S, it.tile, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
                 case 4: det_direct64<4, TT, MODE>(S, it.tile, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
-                default: det_generic64<TT, MODE>(S, it.tile, k, a, b, exw, rb, tabs, cs, lane, Wl, acc); break;
+                default:
+                    if constexpr (GEN)
+                        det_generic64<TT, MODE>(S, it.tile, k, a, b, exw, rb, tabs, cs, lane, Wl, acc);
+                    break;
             }
         }
     }
@@ -962,7 +983,10 @@ __device__ __forceinline__ void item64(const WorkItem &it, const InstDev &I, con
     __syncthreads();
 }
 
-template <typename TT, int MODE, int WT>
+// GEN: the instantiation also evaluates orders 5..8 (elimination with
+// pivoting, whose 8 x 8 arrays live in scratch); expansions of orders up to
+// 4 run the instantiation without them.
+template <typename TT, int MODE, int WT, bool GEN>
 __global__ void __launch_bounds__(WT == 64 ? DET64_THREADS : 1024)
 k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
       const int32_t *__restrict__ bounds, ItemQueues qs,
@@ -1049,7 +1073,7 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
         }
         if (WT == 64) {
             const MoveArgs mv = moves ? moves[it.inst] : m1;
-            item64<TT, MODE>(it, I, S, mv, exl, tab_raw, bounds, tid, nthr, tab0, tab1);
+            item64<TT, MODE, GEN>(it, I, S, mv, exl, tab_raw, bounds, tid, nthr, tab0, tab1);
             continue;
         }
         const int n = S.n, m = S.m, WTP = S.WTP, W = I.W;
@@ -1101,7 +1125,9 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
             case 2: det_loop<2, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
             case 3: det_loop<3, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
             case 4: det_loop<4, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
-            default: det_loop<0, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc); break;
+            default:
+                if constexpr (GEN) det_loop<0, TT, MODE, WT>(it, S, recs, tabs, gs, cs, wl, slot, nslot, acc);
+                break;
         }
         __syncthreads();   // tables no longer needed: reuse LDS for the reduction
         if (MODE == DM_PROPOSE) {
@@ -1140,7 +1166,7 @@ k_det(const InstDev *__restrict__ insts, const WorkItem *__restrict__ items,
     }
 }
 
-template <typename TT, int MODE>
+template <typename TT, int MODE, bool GEN>
 static hipError_t launch_det_wt(int WT, hipStream_t st, const InstDev *d_insts,
                                 const WorkItem *items, const int32_t *bounds,
                                 const ItemQueues &qs, int ex_cap,
@@ -1149,7 +1175,7 @@ static hipError_t launch_det_wt(int WT, hipStream_t st, const InstDev *d_insts,
                                 const double *t1) {
 #define MDE_DET_CASE(X)                                                                     \
     case X: {                                                                               \
-        auto fn = k_det<TT, MODE, X>;                                                       \
+        auto fn = k_det<TT, MODE, X, GEN>;                                                  \
         if (lds > 65536)                                                                    \
             (void)hipFuncSetAttribute((const void *)fn,                                     \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
@@ -1173,22 +1199,29 @@ static hipError_t launch_det_wt(int WT, hipStream_t st, const InstDev *d_insts,
 hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst, const WorkItem *items,
                       const int32_t *bounds, const ItemQueues &qs, int ex_cap, const MoveArgs *d_moves, const MoveArgs &m1,
                       int mode, int prec, int WT, size_t lds, int threads, int grid,
-                      int32_t *counter, const double *tab0, const double *tab1) {
+                      int32_t *counter, const double *tab0, const double *tab1, int max_order) {
     // every instance of one launch uses the same walker tile WT
     (void)n_inst;
     if (qs.off[NXCD] <= 0) return hipSuccess;
+#define MDE_DET_GEN(TT, MD, G)                                                                  \
+    return launch_det_wt<TT, MD, G>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves, m1, lds, \
+                                    threads, grid, counter, tab0, tab1)
+    const bool gen = max_order > 4;
     if (prec == 0) {
-        if (mode == DM_PROPOSE)
-            return launch_det_wt<double, DM_PROPOSE>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves,
-                                                     m1, lds, threads, grid, counter, tab0, tab1);
-        return launch_det_wt<double, DM_VALUES>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves, m1,
-                                                lds, threads, grid, counter, tab0, tab1);
+        if (mode == DM_PROPOSE) {
+            if (gen) MDE_DET_GEN(double, DM_PROPOSE, true);
+            MDE_DET_GEN(double, DM_PROPOSE, false);
+        }
+        if (gen) MDE_DET_GEN(double, DM_VALUES, true);
+        MDE_DET_GEN(double, DM_VALUES, false);
     }
-    if (mode == DM_PROPOSE)
-        return launch_det_wt<float, DM_PROPOSE>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves, m1,
-                                                lds, threads, grid, counter, tab0, tab1);
-    return launch_det_wt<float, DM_VALUES>(WT, st, d_insts, items, bounds, qs, ex_cap, d_moves, m1,
-                                           lds, threads, grid, counter, tab0, tab1);
+    if (mode == DM_PROPOSE) {
+        if (gen) MDE_DET_GEN(float, DM_PROPOSE, true);
+        MDE_DET_GEN(float, DM_PROPOSE, false);
+    }
+    if (gen) MDE_DET_GEN(float, DM_VALUES, true);
+    MDE_DET_GEN(float, DM_VALUES, false);
+#undef MDE_DET_GEN
 }
 
 // ---------------------------------------------------------------------------

@@ -143,7 +143,7 @@ static void apply_default_plan(mde_ctx *c, int W);
 struct mde_group {
     std::vector<mde_ctx *> ctx;
     hipStream_t stream = nullptr;
-    int prec = 0, WT = 1, threads = 256, maxW = 0, nmax = 0, mmax = 0;
+    int prec = 0, WT = 1, threads = 256, maxW = 0, nmax = 0, mmax = 0, max_order = 0;
     size_t lds = 0;
     int grid = 0;
     int ex_cap = 16;
@@ -858,7 +858,7 @@ static mde_status run_values(mde_ctx *c, int s, const double *tab0 = nullptr,
     MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], c->d_bounds[s], sp.queues, sp.ex_cap,
                           nullptr, no_move(), DM_VALUES, c->d.precision, c->WT,
                           std::max<size_t>(sp.lds_val, 16), sp.threads, sp.grid, c->h.counter,
-                          tab0, tab1));
+                          tab0, tab1, sp.max_order));
     c->R_valid[s] = true;
     return MDE_OK;
 }
@@ -1485,7 +1485,7 @@ static mde_status do_propose(mde_ctx *c, int32_t e, const double *orb, double *r
     for (int r = 0; r < reps && !sp.items.empty(); ++r)
         MDE_HIP(c, launch_det(c->stream, c->d_inst, 1, c->d_items[s], c->d_bounds[s], sp.queues, sp.ex_cap,
                               nullptr, m, DM_PROPOSE, c->d.precision, c->WT, sp.lds_prop, sp.threads,
-                              sp.grid, c->h.counter, nullptr, nullptr));
+                              sp.grid, c->h.counter, nullptr, nullptr, sp.max_order));
     if (prof) {
         MDE_HIP(c, hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream));
         c->prof_used++;
@@ -2012,6 +2012,7 @@ static mde_status group_rebuild(mde_group *g) {
     for (int i = 0; i < n; ++i) {
         mde_ctx *c = g->ctx[i];
         g->maxW = std::max(g->maxW, c->W);
+        g->max_order = std::max(g->max_order, std::max(c->sp[0].max_order, c->sp[1].max_order));
         g->nmax = std::max(g->nmax, c->h.nmax);
         g->mmax = std::max(g->mmax, c->h.mmax);
         for (int s = 0; s < 2; ++s) {
@@ -2187,7 +2188,7 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const
         MDE_GFAIL(g, MDE_DEVICE, "propose launch");
     if (launch_det(g->stream, g->d_insts, n, g->d_items, g->d_bounds, g->queues, g->ex_cap, g->d_moves, none,
                    DM_PROPOSE, g->prec, g->WT, g->lds, g->threads, g->grid, g->ctx[0]->h.counter,
-                   nullptr, nullptr) != hipSuccess)
+                   nullptr, nullptr, g->max_order) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "determinant launch");
     if (launch_finish(g->stream, g->d_insts, n, g->maxW, g->d_moves, none, nullptr) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "finish launch");

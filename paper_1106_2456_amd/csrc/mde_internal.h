@@ -214,7 +214,7 @@ hipError_t launch_det(hipStream_t st, const InstDev *d_insts, int n_inst,
                       int ex_cap,
                       const MoveArgs *d_moves, const MoveArgs &m1, int mode, int prec,
                       int WT, size_t lds_bytes, int threads, int grid, int32_t *counter,
-                      const double *tab0, const double *tab1);
+                      const double *tab0, const double *tab1, int max_order);
 // smallest part count of the proposal whose LDS footprint fits lds_max (0: none)
 int propose_split_limit(int nmax, int mmax, int WT, size_t lds_max);
 hipError_t launch_post(hipStream_t st, const InstDev *d_inst, const MoveArgs &m1, int n_tiles,
