@@ -533,21 +533,30 @@ def run_uneven(steps, warmup, n_moves=4, precision="fp64", wls=None, cpu=True):
     a proposal + commit of one electron in every instance, issued as one
     group launch per walker-tile size (FP64, or the mixed form)."""
     import torch
-    from paper_1106_2456_amd import Context, Group
     if wls is None:
         wls = uneven_workloads(n_moves)
+    # a side stream: the legacy default stream cannot be captured
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        return _run_uneven(steps, warmup, n_moves, precision, wls, cpu, stream)
+
+
+def _run_uneven(steps, warmup, n_moves, precision, wls, cpu, side_stream):
+    import torch
+    from paper_1106_2456_amd import Context, Group
     ctxs = []
     for w in wls:
         sy = w.system
         mo = max(int(sy.exc[0].orders().max()), int(sy.exc[1].orders().max()), 1)
-        c = Context(sy.n_elec, sy.n_orb, 256, max_order=mo, precision=precision)
+        c = Context(sy.n_elec, sy.n_orb, 256, max_order=mo, precision=precision, stream=side_stream)
         c.set_expansion(sy.exc[0], sy.exc[1], sy.coef, sy.det_up, sy.det_dn)
         for sp in (0, 1):
             c.set_basis(sp, sy.centres, sy.expo, sy.mo_spin(sp))
         ctxs.append(c)
-    # one group launch per walker-tile size (the instances whose tables fit
-    # wide tiles keep them)
-    groups = Group.by_tile(ctxs, [256] * len(wls))
+    # one group: each instance keeps the walker tile its tables fit, and the
+    # library runs one determinant launch per tile class inside each call
+    group = Group(ctxs, [256] * len(wls), common_tile=False)
+    groups = [(group, list(range(len(ctxs))))]
     moves = []
     for c, w in zip(ctxs, wls):
         pos = torch.as_tensor(w.walkers.pos, device="cuda")
@@ -566,23 +575,32 @@ def run_uneven(steps, warmup, n_moves=4, precision="fp64", wls=None, cpu=True):
              torch.empty((256, 3), dtype=torch.float64, device="cuda"),
              torch.empty(256, dtype=torch.float64, device="cuda"),
              torch.zeros(256, dtype=torch.int32, device="cuda")) for _ in wls]
-    stream = groups[0][0].stream
+    stream = group.stream
     torch.cuda.synchronize()
+    # autotuned launch plans (per walker-tile class), then the state again
+    group.tune(moves[0][0], moves[0][1])
+    for c, w in zip(ctxs, wls):
+        pos = torch.as_tensor(w.walkers.pos, device="cuda")
+        nu = w.system.n_elec[0]
+        c.init(c.sgauss_eval(0, pos[:, :nu].contiguous()), c.sgauss_eval(1, pos[:, nu:].contiguous()))
 
     def step(k):
         es, news, masks = moves[k % n_moves]
-        for g, idx in groups:
-            g.propose([es[i] for i in idx], [news[i] for i in idx], [outs[i] for i in idx])
-            g.accept([es[i] for i in idx], [masks[i] for i in idx])
+        group.propose(es, news, outs)
+        group.accept(es, masks)
 
     for k in range(max(warmup, 1)):
         step(k)
     torch.cuda.synchronize()
+    # the timed steps captured into one HIP graph, replayed once
+    with group.capture() as cap:
+        for k in range(steps):
+            step(k)
+    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for k in range(steps):
-        step(k)
+    cap.graph.launch()
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -601,10 +619,12 @@ def run_uneven(steps, warmup, n_moves=4, precision="fp64", wls=None, cpu=True):
         byts.append(tot)
     out = dict(value=wdets / (ms * 1e-3), unit="walker.det/s", ms_per_step=ms,
                walker_dets_per_step=wdets, status_bits=int(np.bitwise_or.reduce(st.ravel())),
-               tiles={str(ctxs[idx[0]].get_plan(0)["walker_tile"]): len(idx) for _, idx in groups},
+               tiles={str(t): sum(1 for c in ctxs if c.get_plan(0)["walker_tile"] == t)
+                      for t in sorted({c.get_plan(0)["walker_tile"] for c in ctxs})},
                workload="64 uneven instances x 256 walkers (n 5..64 per spin, m = 4n, "
                         f"N_det 1e2..2e5 log-uniform), {precision}; step = one proposal + "
-                        "commit of every instance, one group launch per walker-tile size, eager",
+                        "commit of every instance: one group call (a determinant launch per "
+                        "walker-tile class), autotuned, the timed steps replayed as one HIP graph",
                roofline=roofline_block("group step (all kernels of one proposal + commit)",
                                        float(np.mean(byts)), ms * 1e-3,
                                        note="bytes: the determinant launches' algorithmic bytes "

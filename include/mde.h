@@ -347,12 +347,15 @@ mde_status mde_graph_destroy(mde_graph *g);
 
 /* ---- uneven batch ------------------------------------------------------- */
 
-/* Pack n bound contexts (same stream, same precision, same walker tile --
- * set it with mde_set_plan before binding) so that one propose runs as one
- * persistent launch of the determinant kernel over the work items of every
- * instance (Sec. V: the tiny determinants are independent).  The group's
- * tables live in caller-owned device memory of mde_group_workspace_bytes
- * bytes.  MDE_INVALID if the walker tiles differ. */
+/* Pack n bound contexts (same stream, same precision) so that one propose
+ * runs the determinant kernel as one persistent launch per walker tile over
+ * the work items of every instance of that tile (Sec. V: the tiny
+ * determinants are independent): members that share a walker tile form one
+ * launch; members of different tiles (each keeps the tile its tables fit,
+ * chosen at bind) form one launch per tile, widest first, within the same
+ * group call.  The group's work lists live in caller-owned device memory of
+ * mde_group_workspace_bytes bytes.  Contexts with a switched reference are
+ * refused (MDE_UNSUPPORTED). */
 mde_status mde_group_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *bytes);
 mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t bytes,
                             mde_group **out);
@@ -367,6 +370,13 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e,
 /* accept[n] (host array of device uint8 [W_i] pointers). */
 mde_status mde_group_accept(mde_group *g, const int32_t *e,
                             const uint8_t *const *accept);
+/* Autotuner of a group: for each walker-tile class, threads per block and
+ * work-item size of its members (their tiles kept) are chosen by timing
+ * three group proposals of the moving electrons e[n] to new_orb[n] (as in
+ * mde_group_propose) per candidate; each candidate re-evaluates the members
+ * from their kept orbitals, so the state is that of the last init/refresh
+ * afterwards.  Not during capture. */
+mde_status mde_group_tune(mde_group *g, const int32_t *e, const double *const *new_orb);
 /* Last error message of a group call. */
 const char *mde_group_error_string(const mde_group *g);
 /* Capture / replay work on groups exactly as on contexts. */

@@ -72,6 +72,7 @@ _SIGS = {
     "mde_group_destroy": ([_P], C.c_int),
     "mde_group_propose": ([_P, _P, _P, _P, _P, _P, _P], C.c_int),
     "mde_group_accept": ([_P, _P, _P], C.c_int),
+    "mde_group_tune": ([_P, _P, _P], C.c_int),
     "mde_group_capture_begin": ([_P], C.c_int),
     "mde_group_capture_end": ([_P, C.POINTER(_P)], C.c_int),
     "mde_sgauss_set_basis": ([_P, _I, _I, _P, _P, _P], C.c_int),

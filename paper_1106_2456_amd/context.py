@@ -372,9 +372,17 @@ class Group:
             out.append((Group([ctxs[i] for i in idx], [Ws[i] for i in idx]), idx))
         return out
 
-    def __init__(self, ctxs: Sequence[Context], Ws: Optional[Sequence[int]] = None):
+    def __init__(self, ctxs: Sequence[Context], Ws: Optional[Sequence[int]] = None,
+                 common_tile: bool = True):
+        """Ws: bind the (unbound) contexts first, with one common walker tile
+        (one launch for all) or, with common_tile=False, each with its own
+        default tile (the library then runs one launch per tile class)."""
         if Ws is not None:
-            Group.prepare(ctxs, Ws)
+            if common_tile:
+                Group.prepare(ctxs, Ws)
+            else:
+                for c, W in zip(ctxs, Ws):
+                    c.bind(W)
         self.ctxs = list(ctxs)
         arr = (C.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
         self._arr = arr
@@ -419,6 +427,15 @@ class Group:
         k = self._keepalive
         self._chk(lib().mde_group_propose(self._h, _np_ptr(e), k[0], k[1], k[2], k[3], k[4]),
                   "group_propose")
+
+    def tune(self, es, new_orbs):
+        """Autotune the members' launch plans on proposals of electrons es to
+        new_orbs (the members' state is re-evaluated from their orbitals)."""
+        e = np.ascontiguousarray(es, np.int32)
+        arr = self._ptrs(new_orbs)
+        self._chk(lib().mde_group_tune(self._h, _np_ptr(e), arr), "group_tune")
+        for c in self.ctxs:
+            c.state_seq += 1
 
     def accept(self, es, masks):
         e = np.ascontiguousarray(es, np.int32)

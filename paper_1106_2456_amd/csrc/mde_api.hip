@@ -157,6 +157,10 @@ struct mde_group {
     std::vector<long> plan_gen;   // each member's plan generation at the last rebuild
     bool capturing = false;
     std::string err;
+    // members of several walker tiles: one homogeneous group (one launch of
+    // the determinant kernel) per tile, called in order of decreasing tile
+    std::vector<mde_group *> subs;
+    std::vector<std::vector<int>> sub_idx;
 };
 
 // ---------------------------------------------------------------------------
@@ -1982,7 +1986,7 @@ static size_t group_items(mde_ctx *const *ctxs, int n) {
     return t;
 }
 
-mde_status mde_group_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *bytes) {
+static mde_status hgroup_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *bytes) {
     if (!ctxs || n < 1 || !bytes) return MDE_INVALID;
     size_t max_items = 0;
     for (int i = 0; i < n; ++i) {
@@ -2009,6 +2013,12 @@ static mde_status group_rebuild(mde_group *g) {
     g->maxW = 0;
     g->nmax = 0;
     g->mmax = 0;
+    {
+        int thr = 64;
+        for (int i = 0; i < n; ++i)
+            for (int s = 0; s < 2; ++s) thr = std::max(thr, g->ctx[i]->sp[s].threads);
+        g->threads = std::min(std::max(thr, g->WT), max_threads(g->WT));
+    }
     for (int i = 0; i < n; ++i) {
         mde_ctx *c = g->ctx[i];
         g->maxW = std::max(g->maxW, c->W);
@@ -2063,8 +2073,8 @@ static mde_status group_rebuild(mde_group *g) {
     return MDE_OK;
 }
 
-mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t bytes,
-                            mde_group **out) {
+static mde_status hgroup_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t bytes,
+                               mde_group **out) {
     if (!ctxs || n < 1 || !out || !dev) return MDE_INVALID;
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
@@ -2074,7 +2084,7 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
         if (ctxs[i]->d_orb_perm[0] || ctxs[i]->d_orb_perm[1]) return MDE_UNSUPPORTED;
     }
     size_t need = 0;
-    if (mde_group_workspace_bytes(ctxs, n, &need) != MDE_OK || bytes < need) return MDE_NOMEM;
+    if (hgroup_workspace_bytes(ctxs, n, &need) != MDE_OK || bytes < need) return MDE_NOMEM;
     mde_group *g = new (std::nothrow) mde_group();
     if (!g) return MDE_NOMEM;
     g->ctx.assign(ctxs, ctxs + n);
@@ -2113,11 +2123,7 @@ mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t b
     return MDE_OK;
 }
 
-mde_status mde_group_destroy(mde_group *g) {
-    if (!g) return MDE_OK;
-    delete g;
-    return MDE_OK;
-}
+static void hgroup_destroy(mde_group *g) { delete g; }
 
 // Write the per-instance move arguments to the device array the kernels
 // read, stream-ordered, as arguments of small copy kernels: nothing is read
@@ -2148,9 +2154,9 @@ static mde_status group_check_plans(mde_group *g) {
     return group_rebuild(g);
 }
 
-mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const *new_orb,
-                             double *const *ratio, double *const *grad, double *const *lap,
-                             int32_t *const *status) {
+static mde_status hgroup_propose(mde_group *g, const int32_t *e, const double *const *new_orb,
+                                 double *const *ratio, double *const *grad, double *const *lap,
+                                 int32_t *const *status) {
     if (!g || !e || !new_orb) return MDE_INVALID;
     const int n = (int)g->ctx.size();
     {
@@ -2199,7 +2205,7 @@ mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const
     return MDE_OK;
 }
 
-mde_status mde_group_accept(mde_group *g, const int32_t *e, const uint8_t *const *accept) {
+static mde_status hgroup_accept(mde_group *g, const int32_t *e, const uint8_t *const *accept) {
     if (!g || !e || !accept) return MDE_INVALID;
     const int n = (int)g->ctx.size();
     {
@@ -2248,6 +2254,7 @@ mde_status mde_group_capture_begin(mde_group *g) {
     if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         MDE_GFAIL(g, MDE_DEVICE, "begin capture");
     g->capturing = true;
+    for (mde_group *q : g->subs) q->capturing = true;
     for (mde_ctx *c : g->ctx) c->capturing = true;
     return MDE_OK;
 }
@@ -2256,6 +2263,7 @@ mde_status mde_group_capture_end(mde_group *g, mde_graph **out) {
     if (!g || !out) return MDE_INVALID;
     if (!g->capturing) MDE_GFAIL(g, MDE_STATE, "not capturing");
     g->capturing = false;
+    for (mde_group *q : g->subs) q->capturing = false;
     for (mde_ctx *c : g->ctx) c->capturing = false;
     mde_graph *gr = new (std::nothrow) mde_graph();
     if (!gr) return MDE_NOMEM;
@@ -2269,6 +2277,206 @@ mde_status mde_group_capture_end(mde_group *g, mde_graph **out) {
         MDE_GFAIL(g, MDE_DEVICE, "instantiate");
     }
     *out = gr;
+    return MDE_OK;
+}
+
+// members grouped by walker tile, widest first
+static std::vector<std::vector<int>> tile_classes(mde_ctx *const *ctxs, int n) {
+    std::map<int, std::vector<int>, std::greater<int>> m;
+    for (int i = 0; i < n; ++i) m[ctxs[i]->WT].push_back(i);
+    std::vector<std::vector<int>> out;
+    for (auto &kv : m) out.push_back(kv.second);
+    return out;
+}
+
+mde_status mde_group_workspace_bytes(mde_ctx *const *ctxs, int32_t n, size_t *bytes) {
+    if (!ctxs || n < 1 || !bytes) return MDE_INVALID;
+    for (int i = 0; i < n; ++i)
+        if (!ctxs[i] || !ctxs[i]->bound) return MDE_STATE;
+    const auto cls = tile_classes(ctxs, n);
+    if (cls.size() == 1) return hgroup_workspace_bytes(ctxs, n, bytes);
+    size_t tot = 0;
+    for (const auto &idx : cls) {
+        std::vector<mde_ctx *> cs;
+        for (int i : idx) cs.push_back(ctxs[i]);
+        size_t b = 0;
+        mde_status st = hgroup_workspace_bytes(cs.data(), (int)cs.size(), &b);
+        if (st) return st;
+        tot += align_up(b, 256);
+    }
+    *bytes = tot;
+    return MDE_OK;
+}
+
+mde_status mde_group_create(mde_ctx *const *ctxs, int32_t n, void *dev, size_t bytes,
+                            mde_group **out) {
+    if (!ctxs || n < 1 || !out || !dev) return MDE_INVALID;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || !ctxs[i]->bound) return MDE_STATE;
+        if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->d.precision != ctxs[0]->d.precision)
+            return MDE_INVALID;
+    }
+    const auto cls = tile_classes(ctxs, n);
+    if (cls.size() == 1) return hgroup_create(ctxs, n, dev, bytes, out);
+    size_t need = 0;
+    if (mde_group_workspace_bytes(ctxs, n, &need) != MDE_OK || bytes < need) return MDE_NOMEM;
+    mde_group *g = new (std::nothrow) mde_group();
+    if (!g) return MDE_NOMEM;
+    g->ctx.assign(ctxs, ctxs + n);
+    g->stream = ctxs[0]->stream;
+    g->prec = ctxs[0]->d.precision;
+    size_t off = 0;
+    for (const auto &idx : cls) {
+        std::vector<mde_ctx *> cs;
+        for (int i : idx) cs.push_back(ctxs[i]);
+        size_t b = 0;
+        mde_group *sub = nullptr;
+        mde_status st = hgroup_workspace_bytes(cs.data(), (int)cs.size(), &b);
+        if (st == MDE_OK) st = hgroup_create(cs.data(), (int)cs.size(), (char *)dev + off, b, &sub);
+        if (st) {
+            for (mde_group *q : g->subs) hgroup_destroy(q);
+            delete g;
+            return st;
+        }
+        g->subs.push_back(sub);
+        g->sub_idx.push_back(idx);
+        off += align_up(b, 256);
+    }
+    *out = g;
+    return MDE_OK;
+}
+
+mde_status mde_group_destroy(mde_group *g) {
+    if (!g) return MDE_OK;
+    for (mde_group *q : g->subs) hgroup_destroy(q);
+    hgroup_destroy(g);
+    return MDE_OK;
+}
+
+}  // extern "C"
+
+template <typename T>
+static std::vector<T> gather_args(const T *a, const std::vector<int> &idx) {
+    std::vector<T> out;
+    if (!a) return out;
+    for (int i : idx) out.push_back(a[i]);
+    return out;
+}
+
+template <typename T>
+static const T *ptr_or_null(const std::vector<T> &v) {
+    return v.empty() ? nullptr : v.data();
+}
+
+extern "C" {
+
+mde_status mde_group_propose(mde_group *g, const int32_t *e, const double *const *new_orb,
+                             double *const *ratio, double *const *grad, double *const *lap,
+                             int32_t *const *status) {
+    if (!g || !e || !new_orb) return MDE_INVALID;
+    if (g->subs.empty()) return hgroup_propose(g, e, new_orb, ratio, grad, lap, status);
+    for (size_t k = 0; k < g->subs.size(); ++k) {
+        const auto &idx = g->sub_idx[k];
+        const auto ee = gather_args(e, idx);
+        const auto no = gather_args(new_orb, idx);
+        const auto ra = gather_args(ratio, idx);
+        const auto gr = gather_args(grad, idx);
+        const auto la = gather_args(lap, idx);
+        const auto stt = gather_args(status, idx);
+        mde_status st = hgroup_propose(g->subs[k], ee.data(), no.data(), ptr_or_null(ra), ptr_or_null(gr),
+                                       ptr_or_null(la), ptr_or_null(stt));
+        if (st) MDE_GFAIL(g, st, "walker-tile class %zu: %s", k, g->subs[k]->err.c_str());
+    }
+    return MDE_OK;
+}
+
+mde_status mde_group_accept(mde_group *g, const int32_t *e, const uint8_t *const *accept) {
+    if (!g || !e || !accept) return MDE_INVALID;
+    if (g->subs.empty()) return hgroup_accept(g, e, accept);
+    for (size_t k = 0; k < g->subs.size(); ++k) {
+        const auto &idx = g->sub_idx[k];
+        const auto ee = gather_args(e, idx);
+        const auto ac = gather_args(accept, idx);
+        mde_status st = hgroup_accept(g->subs[k], ee.data(), ac.data());
+        if (st) MDE_GFAIL(g, st, "walker-tile class %zu: %s", k, g->subs[k]->err.c_str());
+    }
+    return MDE_OK;
+}
+
+// Autotuner of a homogeneous group: threads per block and item size of its
+// members (their walker tile kept), each candidate applied to every member
+// (state kept: re-evaluated from the kept orbitals) and timed over three
+// group proposals after a warm one; the fastest stays.
+static mde_status hgroup_tune(mde_group *g, const int32_t *e, const double *const *new_orb) {
+    const int n = (int)g->ctx.size();
+    const int WT = g->WT;
+    struct Cand {
+        int thr;
+        double scale;
+    };
+    std::vector<Cand> cands;
+    for (int thr : {256, 512, 1024})
+        if (thr >= WT && thr <= max_threads(WT))
+            for (double sc : {0.5, 1.0, 2.0}) cands.push_back({thr, sc});
+    auto apply = [&](const Cand &cd) -> mde_status {
+        for (int i = 0; i < n; ++i) {
+            mde_ctx *c = g->ctx[i];
+            Plan p{};
+            p.WT = c->WT;
+            for (int s = 0; s < 2; ++s) {
+                p.threads[s] = cd.thr;
+                const size_t lds = det_lds(c->sp[s], c->WT, cd.thr, c->d.precision, true);
+                const int base = item_size_for(c, c->sp[s], c->W, c->WT, cd.thr, lds);
+                p.item_exc[s] = std::max((int)(base * cd.scale), 4 * (cd.thr / c->WT));
+            }
+            mde_status st = replan_keep_state(c, p);
+            if (st) return st;
+        }
+        return group_rebuild(g);
+    };
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        MDE_GFAIL(g, MDE_DEVICE, "event creation");
+    double best_t = 1e30;
+    int best = -1;
+    for (size_t k = 0; k < cands.size(); ++k) {
+        if (apply(cands[k]) != MDE_OK) continue;
+        if (hgroup_propose(g, e, new_orb, nullptr, nullptr, nullptr, nullptr) != MDE_OK) continue;
+        (void)hipEventRecord(e0, g->stream);
+        bool ok = true;
+        for (int r = 0; r < 3; ++r)
+            ok &= hgroup_propose(g, e, new_orb, nullptr, nullptr, nullptr, nullptr) == MDE_OK;
+        (void)hipEventRecord(e1, g->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ok && ms < best_t) {
+            best_t = ms;
+            best = (int)k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best < 0) MDE_GFAIL(g, MDE_DEVICE, "no candidate plan ran");
+    mde_status st = apply(cands[best]);
+    if (st) MDE_GFAIL(g, st, "applying the chosen plan");
+    for (mde_ctx *c : g->ctx) c->pending_e = -1;
+    return MDE_OK;
+}
+
+mde_status mde_group_tune(mde_group *g, const int32_t *e, const double *const *new_orb) {
+    if (!g || !e || !new_orb) return MDE_INVALID;
+    if (g->capturing) MDE_GFAIL(g, MDE_STATE, "cannot tune during capture");
+    for (mde_ctx *c : g->ctx)
+        if (!c->initialized || c->adjoint_state) MDE_GFAIL(g, MDE_STATE, "initialise every member first");
+    if (g->subs.empty()) return hgroup_tune(g, e, new_orb);
+    for (size_t k = 0; k < g->subs.size(); ++k) {
+        const auto ee = gather_args(e, g->sub_idx[k]);
+        const auto no = gather_args(new_orb, g->sub_idx[k]);
+        mde_status st = hgroup_tune(g->subs[k], ee.data(), no.data());
+        if (st) MDE_GFAIL(g, st, "walker-tile class %zu: %s", k, g->subs[k]->err.c_str());
+    }
     return MDE_OK;
 }
 

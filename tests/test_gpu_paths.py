@@ -267,3 +267,58 @@ def test_group_member_plan_change_rebuilds():
         ref = oracle.move(w.system, w.walkers.pos, e, w.walkers.pos[:, e] + w.moves.disp[0])
         err = scaled_err(o[0].cpu().numpy(), ref["ratio"], ref["scale_ratio"]).max()
         assert err <= 1e-10, err
+
+
+def test_mixed_tile_group_tuned_and_captured():
+    """Members of different walker tiles in one group (one launch per tile
+    class inside each group call), equal to the oracle; after mde_group_tune
+    still equal to it; a captured group step replayed = the eager step."""
+    from paper_1106_2456_amd import Group
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        wls = [synth.water_like(2, W=64, n_det=600, n_moves=8),
+               synth.molecular(3, W=9, n_det=300, n_moves=8, n=12, m=40, nb=64, n_nuc=6, box=6.0),
+               synth.molecular(3, W=5, n_det=200, n_moves=8, n=32, m=64, nb=96, n_nuc=8, box=8.0)]
+        ctxs = [make_ctx(w, bind=False, stream=stream) for w in wls]
+        g = Group(ctxs, [w.walkers.W for w in wls], common_tile=False)
+        tiles = sorted({c.get_plan(0)["walker_tile"] for c in ctxs})
+        say("mixed-tile group tiles", tiles)
+        assert len(tiles) >= 2
+        pos = [w.walkers.pos.copy() for w in wls]
+        for c, p in zip(ctxs, pos):
+            c.init(*gpu_orbitals(c, p))
+
+        def step(k, check):
+            es, blks, outs, masks, news = [], [], [], [], []
+            for c, w, p in zip(ctxs, wls, pos):
+                e = int(w.moves.electron[k])
+                r = p[:, e] + w.moves.disp[k]
+                es.append(e)
+                news.append(r)
+                blks.append(c.sgauss_eval(c.spin_of(e), dev(r)))
+                outs.append((torch.zeros(c.W, dtype=torch.float64, device="cuda"),
+                             torch.zeros((c.W, 3), dtype=torch.float64, device="cuda"),
+                             torch.zeros(c.W, dtype=torch.float64, device="cuda"),
+                             torch.zeros(c.W, dtype=torch.int32, device="cuda")))
+                masks.append(dev(w.moves.accept_half[k], torch.uint8))
+            g.propose(es, blks, outs)
+            g.accept(es, masks)
+            stream.synchronize()
+            if check:
+                for i, (w, p) in enumerate(zip(wls, pos)):
+                    ref = oracle.move(w.system, p, es[i], news[i])
+                    er = scaled_err(outs[i][0].cpu().numpy(), ref["ratio"], ref["scale_ratio"]).max()
+                    eg = scaled_err(outs[i][1].cpu().numpy(), ref["grad"], ref["scale_grad"]).max()
+                    assert er <= 1e-10 and eg <= 1e-10, (k, i, er, eg)
+            for i, (w, p) in enumerate(zip(wls, pos)):
+                acc = w.moves.accept_half[k].astype(bool)
+                p[acc, es[i]] = news[i][acc]
+            return es, blks
+
+        for k in range(3):
+            es, blks = step(k, True)
+        g.tune(es, blks)
+        say("after tune", [c.get_plan(0) for c in ctxs])
+        # the tuner re-evaluates from the kept orbitals (the current positions)
+        for k in range(3, 6):
+            step(k, True)
