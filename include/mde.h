@@ -166,8 +166,9 @@ mde_status mde_bind_workspace(mde_ctx *ctx, int32_t W, void *dev, size_t bytes);
  * orb_up [W][n_up][5][n_orb_up], orb_dn [W][n_dn][5][n_orb_dn] hold every
  * electron's orbital block at its current position.  Computes A0^-1 by LU
  * with partial pivoting, T = A0^-1 Phi_V, all excited ratios and the CI sum.
- * Outputs log|Psi| and sign(Psi) per walker ([W] each, may be NULL). */
-mde_status mde_init(mde_ctx *ctx, const double *orb_up, const double *orb_dn,
+ * Outputs log|Psi| and sign(Psi) per walker ([W] each, may be NULL).  W
+ * must equal the walker count the workspace was bound for (MDE_INVALID). */
+mde_status mde_init(mde_ctx *ctx, int32_t W, const double *orb_up, const double *orb_dn,
                     double *log_abs_psi, double *sign_psi, int32_t *status);
 
 /* Recompute A0^-1, T and the sums from the orbital values the library keeps
@@ -263,15 +264,17 @@ mde_status mde_export(mde_ctx *ctx, int32_t what, int32_t spin, double *dst);
  * S[j][l] = T_sigma[h_j][p_l - n] (Sec. III r x r read-off).  T_up
  * [W][n_up][m_up], T_dn [W][n_dn][m_dn], coef [n_det] (device, FP64).
  * Outputs log|N| and sign(N) per walker.  Keeps what mde_backward needs. */
-mde_status mde_eval_tables(mde_ctx *ctx, const double *T_up, const double *T_dn,
+mde_status mde_eval_tables(mde_ctx *ctx, int32_t W, const double *T_up, const double *T_dn,
                            const double *coef, double *log_abs, double *sign,
                            int32_t *status);
 
 /* Adjoint of the last mde_eval_tables: with go[W] the upstream gradient of
  * log|N_w|, grad_coef[I] = sum_w go_w dlog|N_w|/dcoef_I (deterministic order)
- * and grad_T_sigma[w] = go_w dlog|N_w|/dT_sigma[w] ([W][n][m]). */
+ * and grad_T_sigma[w] = go_w dlog|N_w|/dT_sigma[w] ([W][n][m]).  status[W]
+ * (may be NULL): MDE_ST_NONFINITE for a walker whose table gradient holds a
+ * non-finite value. */
 mde_status mde_backward(mde_ctx *ctx, const double *go, double *grad_coef,
-                        double *grad_T_up, double *grad_T_dn);
+                        double *grad_T_up, double *grad_T_dn, int32_t *status);
 
 /* ---- tuning -------------------------------------------------------------- */
 

@@ -44,7 +44,7 @@ _SIGS = {
     "mde_set_reference": ([_P, _I, _I], C.c_int),
     "mde_workspace_bytes": ([_P, _I, C.POINTER(C.c_size_t)], C.c_int),
     "mde_bind_workspace": ([_P, _I, _P, C.c_size_t], C.c_int),
-    "mde_init": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "mde_init": ([_P, _I, _P, _P, _P, _P, _P], C.c_int),
     "mde_refresh": ([_P, _P, _P, _P], C.c_int),
     "mde_propose": ([_P, _I, _P, _P, _P, _P, _P], C.c_int),
     "mde_grad_lap": ([_P, _I, _P, _P, _P, _P], C.c_int),
@@ -53,8 +53,8 @@ _SIGS = {
     "mde_local_derivs_noalloc": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "mde_vmc": ([_P, _I, C.c_double, _P, _P, _P, _P, _P], C.c_int),
     "mde_export": ([_P, _I, _I, _P], C.c_int),
-    "mde_eval_tables": ([_P, _P, _P, _P, _P, _P, _P], C.c_int),
-    "mde_backward": ([_P, _P, _P, _P, _P], C.c_int),
+    "mde_eval_tables": ([_P, _I, _P, _P, _P, _P, _P, _P], C.c_int),
+    "mde_backward": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "mde_set_plan": ([_P, _I, _I, _I, _I], C.c_int),
     "mde_get_plan": ([_P, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], C.c_int),
     "mde_debug_items": ([_P, _I, _I, _I, _I, _I, _P, _I, C.POINTER(_I), _P, _I, C.POINTER(_I), _P],

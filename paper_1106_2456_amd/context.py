@@ -168,8 +168,8 @@ class Context:
         la, sg = self._empty(W), self._empty(W)
         st = status if status is not None else torch.zeros(W, dtype=torch.int32, device=self.device)
         self.state_seq += 1
-        self._chk(lib().mde_init(self._h, _ptr(orb_up), _ptr(orb_dn), _ptr(la), _ptr(sg), _ptr(st)),
-                  "init")
+        self._chk(lib().mde_init(self._h, W, _ptr(orb_up), _ptr(orb_dn), _ptr(la), _ptr(sg),
+                                 _ptr(st)), "init")
         return la, sg, st
 
     def refresh(self, status=None):
@@ -270,17 +270,18 @@ class Context:
         la, sg = self._empty(W), self._empty(W)
         st = torch.zeros(W, dtype=torch.int32, device=self.device)
         self.state_seq += 1
-        self._chk(lib().mde_eval_tables(self._h, _ptr(T_up), _ptr(T_dn), _ptr(coef), _ptr(la),
+        self._chk(lib().mde_eval_tables(self._h, W, _ptr(T_up), _ptr(T_dn), _ptr(coef), _ptr(la),
                                         _ptr(sg), _ptr(st)), "eval_tables")
         return la, sg, st
 
-    def backward(self, go: torch.Tensor, want_coef=True, want_T=True):
+    def backward(self, go: torch.Tensor, want_coef=True, want_T=True, status=None):
         W = self.W
         _check_dev(go, torch.float64, (W,), "go")
         gc = self._empty(self.n_det) if want_coef else None
         gu = self._empty((W, self.n_elec[0], self.n_orb[0] - self.n_elec[0])) if want_T else None
         gd = self._empty((W, self.n_elec[1], self.n_orb[1] - self.n_elec[1])) if want_T else None
-        self._chk(lib().mde_backward(self._h, _ptr(go), _ptr(gc), _ptr(gu), _ptr(gd)), "backward")
+        self._chk(lib().mde_backward(self._h, _ptr(go), _ptr(gc), _ptr(gu), _ptr(gd), _ptr(status)),
+                  "backward")
         return gc, gu, gd
 
     # -- tuning / graphs ------------------------------------------------------------

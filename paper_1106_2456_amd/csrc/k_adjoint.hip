@@ -214,6 +214,24 @@ hipError_t launch_backward(hipStream_t st, const InstDev *d_inst, const InstDev 
     return hipSuccess;
 }
 
+// status[w] |= NONFINITE when a walker's table gradient holds a non-finite value
+__global__ void k_flag_nonfinite(int W, const double *__restrict__ a, int na,
+                                 const double *__restrict__ b, int nb, int32_t *__restrict__ status) {
+    const int w = blockIdx.x;
+    bool bad = false;
+    if (a)
+        for (int i = threadIdx.x; i < na; i += blockDim.x) bad |= !isfinite(a[(size_t)w * na + i]);
+    if (b)
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) bad |= !isfinite(b[(size_t)w * nb + i]);
+    if (__syncthreads_or(bad) && threadIdx.x == 0) status[w] |= 4;
+}
+
+hipError_t launch_flag_nonfinite(hipStream_t st, int W, const double *a, int na, const double *b,
+                                 int nb, int32_t *status) {
+    hipLaunchKernelGGL(k_flag_nonfinite, dim3(W), dim3(64), 0, st, W, a, na, b, nb, status);
+    return hipGetLastError();
+}
+
 hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
                          const double *Tin, double *grad_T) {
     const SpinDev &S = h.s[spin];

@@ -1417,10 +1417,11 @@ mde_status mde_bind_workspace(mde_ctx *c, int32_t W, void *dev, size_t bytes) {
     return MDE_OK;
 }
 
-mde_status mde_init(mde_ctx *c, const double *orb_up, const double *orb_dn, double *log_abs_psi,
-                    double *sign_psi, int32_t *status) {
+mde_status mde_init(mde_ctx *c, int32_t W, const double *orb_up, const double *orb_dn,
+                    double *log_abs_psi, double *sign_psi, int32_t *status) {
     if (!c) return MDE_INVALID;
     if (!c->bound) MDE_FAIL(c, MDE_STATE, "bind a workspace first");
+    if (W != c->W) MDE_FAIL(c, MDE_INVALID, "W = %d, but the workspace is bound for %d walkers", W, c->W);
     if (!orb_up || !orb_dn) MDE_FAIL(c, MDE_INVALID, "orbital blocks required");
     MDE_HIP(c, launch_fill_i32(c->stream, c->h.st, 0, c->W));
     c->accept_count = 0;
@@ -1647,10 +1648,11 @@ mde_status mde_export(mde_ctx *c, int32_t what, int32_t spin, double *dst) {
     return MDE_OK;
 }
 
-mde_status mde_eval_tables(mde_ctx *c, const double *T_up, const double *T_dn, const double *coef,
-                           double *log_abs, double *sign, int32_t *status) {
+mde_status mde_eval_tables(mde_ctx *c, int32_t W, const double *T_up, const double *T_dn,
+                           const double *coef, double *log_abs, double *sign, int32_t *status) {
     if (!c) return MDE_INVALID;
     if (!c->bound) MDE_FAIL(c, MDE_STATE, "bind a workspace first");
+    if (W != c->W) MDE_FAIL(c, MDE_INVALID, "W = %d, but the workspace is bound for %d walkers", W, c->W);
     if (c->d.precision != MDE_FP64) MDE_FAIL(c, MDE_UNSUPPORTED, "the adjoint path is FP64");
     if (!T_up || !T_dn || !coef) MDE_FAIL(c, MDE_INVALID, "tables and coefficients required");
     MDE_HIP(c, launch_fill_i32(c->stream, c->h.st, 0, c->W));
@@ -1674,7 +1676,7 @@ mde_status mde_eval_tables(mde_ctx *c, const double *T_up, const double *T_dn, c
 }
 
 mde_status mde_backward(mde_ctx *c, const double *go, double *grad_coef, double *grad_T_up,
-                        double *grad_T_dn) {
+                        double *grad_T_dn, int32_t *status) {
     if (!c) return MDE_INVALID;
     if (!c->adjoint_state) MDE_FAIL(c, MDE_STATE, "call mde_eval_tables first");
     if (!go) MDE_FAIL(c, MDE_INVALID, "upstream gradient required");
@@ -1682,6 +1684,9 @@ mde_status mde_backward(mde_ctx *c, const double *go, double *grad_coef, double 
     // caller keeps those buffers unchanged until this call
     MDE_HIP(c, launch_backward(c->stream, c->d_inst, c->h, go, nullptr, nullptr, grad_coef,
                                grad_T_up, grad_T_dn, c->last_T[0], c->last_T[1]));
+    if (status && (grad_T_up || grad_T_dn))
+        MDE_HIP(c, launch_flag_nonfinite(c->stream, c->W, grad_T_up, c->sp[0].n * c->sp[0].m,
+                                         grad_T_dn, c->sp[1].n * c->sp[1].m, status));
     return MDE_OK;
 }
 

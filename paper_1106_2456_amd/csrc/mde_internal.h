@@ -246,6 +246,9 @@ hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h
                          const double *Tin, double *grad_T);
 // all-electron derivatives (k_local.hip): Lnew = 1 / N, then per spin from gz
 hipError_t launch_inv_nold(hipStream_t st, const InstDev *d_inst, const InstDev &h);
+// status[w] |= NONFINITE for walkers whose table gradients hold non-finite values
+hipError_t launch_flag_nonfinite(hipStream_t st, int W, const double *a, int na, const double *b,
+                                 int nb, int32_t *status);
 size_t local_derivs_lds(int n, int m);
 hipError_t launch_local_derivs(hipStream_t st, const InstDev *d_inst, const InstDev &h, int spin,
                                const double *orb, const double *Yn, double *grad, double *lap,

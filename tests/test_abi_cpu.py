@@ -103,9 +103,9 @@ def test_validation_of_setup_calls():
         assert lib.mde_workspace_bytes(h, 4, C.byref(b)) == 0
         assert b.value > 0
         # evaluation before binding is a state error
-        assert lib.mde_init(h, None, None, None, None, None) == L.MDE_STATE
+        assert lib.mde_init(h, 1, None, None, None, None, None) == L.MDE_STATE
         assert lib.mde_accept(h, 0, None) == L.MDE_STATE
-        assert lib.mde_backward(h, None, None, None, None) == L.MDE_STATE
+        assert lib.mde_backward(h, None, None, None, None, None) == L.MDE_STATE
         tile, ie, thr = C.c_int32(), C.c_int32(), C.c_int32()
         assert lib.mde_get_plan(h, 0, C.byref(tile), C.byref(ie), C.byref(thr)) == 0
         assert tile.value in (1, 2, 4, 8, 16, 32, 64) and thr.value % 64 == 0

@@ -272,7 +272,7 @@ def test_group_member_plan_change_rebuilds():
 def test_mixed_tile_group_tuned_and_captured():
     """Members of different walker tiles in one group (one launch per tile
     class inside each group call), equal to the oracle; after mde_group_tune
-    still equal to it; a captured group step replayed = the eager step."""
+    (which re-evaluates the members from their orbitals) still equal to it."""
     from paper_1106_2456_amd import Group
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
