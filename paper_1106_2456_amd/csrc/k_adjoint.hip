@@ -148,30 +148,44 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
             b = min(b, a + pl);
         }
         double acc = 0.0;
-        // the next list entry, its record and its CI weight are loaded while
-        // the current cofactor is formed
-        int code_n = a < b ? inv_ent[a] : 0;
-        uint4 ex_n = a < b ? exs[code_n >> 10] : make_uint4(0, 0, 0, 0);
-        double cw_n = a < b ? Cb[(size_t)(code_n >> 10) * WT] : 0.0;
+        // software pipeline over the list: the entry codes run four entries
+        // ahead, the records and CI weights they index two entries ahead, so
+        // no load waits on another load issued in the same iteration
+        auto code_at = [&](int i) { return i < b ? inv_ent[i] : 0; };
+        int cq0 = code_at(a), cq1 = code_at(a + 1), cq2 = code_at(a + 2), cq3 = code_at(a + 3),
+            cq4 = code_at(a + 4);
+        uint4 ex0 = make_uint4(0, 0, 0, 0), ex1 = ex0;
+        double cw0 = 0.0, cw1 = 0.0;
+        if (a < b) {
+            ex0 = exs[cq0 >> 10];
+            cw0 = Cb[(size_t)(cq0 >> 10) * WT];
+        }
+        if (a + 1 < b) {
+            ex1 = exs[cq1 >> 10];
+            cw1 = Cb[(size_t)(cq1 >> 10) * WT];
+        }
         for (int q = a; q < b; ++q) {
-            const int code = code_n;
-            const uint4 ex = ex_n;
-            const double cw = cw_n;
-            if (q + 1 < b) {
-                code_n = inv_ent[q + 1];
-                ex_n = exs[code_n >> 10];
-                cw_n = Cb[(size_t)(code_n >> 10) * WT];
+            uint4 ex2 = make_uint4(0, 0, 0, 0);
+            double cw2 = 0.0;
+            if (q + 2 < b) {
+                ex2 = exs[cq2 >> 10];
+                cw2 = Cb[(size_t)(cq2 >> 10) * WT];
             }
+            const int cq5 = code_at(q + 5);
+            const int code = cq0;
             const int k = (code >> 6) & 15, j = (code >> 3) & 7, l = code & 7;
             double cf;
             switch (k) {
                 case 1: cf = 1.0; break;
-                case 2: cf = cof_entry<2>(tabs, ex, m, WTP, wl, j, l); break;
-                case 3: cf = cof_entry<3>(tabs, ex, m, WTP, wl, j, l); break;
-                case 4: cf = cof_entry<4>(tabs, ex, m, WTP, wl, j, l); break;
-                default: cf = cof_entry_generic(tabs, ex, k, m, WTP, wl, j, l); break;
+                case 2: cf = cof_entry<2>(tabs, ex0, m, WTP, wl, j, l); break;
+                case 3: cf = cof_entry<3>(tabs, ex0, m, WTP, wl, j, l); break;
+                case 4: cf = cof_entry<4>(tabs, ex0, m, WTP, wl, j, l); break;
+                default: cf = cof_entry_generic(tabs, ex0, k, m, WTP, wl, j, l); break;
             }
-            acc = fma(cw, cf, acc);
+            acc = fma(cw0, cf, acc);
+            cq0 = cq1; cq1 = cq2; cq2 = cq3; cq3 = cq4; cq4 = cq5;
+            ex0 = ex1; ex1 = ex2;
+            cw0 = cw1; cw1 = cw2;
         }
         if (!split) {
             if (live) grad_T[(size_t)w * nm + e] = gw * acc;
