@@ -96,16 +96,23 @@ __device__ double cof_entry_generic(const double *tabs, const uint4 &ex, int k, 
     return y[l];
 }
 
+// table-gradient launch shape: with the lists split over a block's slots,
+// GT_SPLIT_ENTRIES consecutive entries per block (the tile's table staged
+// once for all of them) on GT_SPLIT_THREADS threads
+constexpr int GT_MAX_THREADS = 512;
+constexpr int GT_SPLIT_ENTRIES = 2;
+constexpr int GT_SPLIT_THREADS = 512;
+
 // grad_T_sigma: block (walker tile, part) stages the tile's table in LDS once
-// and takes the part's contiguous range of table entries.  With one entry
-// per part (wide tiles: few tiles, short tables) the entry's inverted list
-// is split over the block's slots (lanes of a slot are the tile's walkers)
-// and the slot sums are added in slot order; otherwise each entry's list is
-// summed by one lane of one slot in list order.  Either way every output
-// element is one fixed-order sum.
-__global__ void __launch_bounds__(256)
+// and takes the part's contiguous range of table entries.  In the split form
+// (wide tiles: few tiles, short tables; a few entries per part) each entry's
+// inverted list is split over the block's slots (lanes of a slot are the
+// tile's walkers) and the slot sums are added in slot order; otherwise each
+// entry's list is summed by one lane of one slot in list order.  Either way
+// every output element is one fixed-order sum.
+__global__ void __launch_bounds__(GT_MAX_THREADS)
 k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__ Tin,
-         double *__restrict__ grad_T, int parts) {
+         double *__restrict__ grad_T, int parts, int split) {
     const InstDev &I = insts[0];
     const SpinDev &S = I.s[spin];
     const int n = S.n, m = S.m, WT = S.WT, WTP = S.WTP, W = I.W;
@@ -137,7 +144,6 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
     const auto inv_off = MDE_G(int32_t, S.inv_off);
     const auto inv_ent = MDE_G(int32_t, S.inv_ent);
     const uint4 *__restrict__ exs = S.ex;
-    const bool split = parts == nm;
     const int per = (nm + parts - 1) / parts;
     const int e_begin = part * per, e_end = min(nm, e_begin + per);
     for (int e = e_begin + (split ? 0 : slot); e < e_end; e += (split ? 1 : nslot)) {
@@ -191,7 +197,7 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
             if (live) grad_T[(size_t)w * nm + e] = gw * acc;
             continue;
         }
-        __shared__ double red[256];
+        __shared__ double red[GT_MAX_THREADS];
         red[slot * WT + wl] = acc;
         __syncthreads();
         if (slot == 0 && live) {
@@ -199,6 +205,7 @@ k_grad_T(const InstDev *__restrict__ insts, int spin, const double *__restrict__
             for (int v = 0; v < nslot; ++v) sum += red[v * WT + wl];
             grad_T[(size_t)w * nm + e] = gw * sum;
         }
+        __syncthreads();   // red is rewritten for the block's next entry
     }
 }
 
@@ -254,15 +261,17 @@ hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)k_grad_T,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    // parts per tile: one entry per block (its list split over the block's
-    // slots) while that stays within 2^16 blocks, else enough ranges of
-    // entries to cover the chip about four times over
+    // parts per tile: GT_SPLIT_ENTRIES entries per block (their lists split
+    // over the block's slots) while one entry per block would stay within
+    // 2^16 blocks, else enough ranges of entries to cover the chip about four
+    // times over
     const int nm = S.n * S.m;
-    const int parts = (size_t)S.n_tiles * nm <= 65536
-                          ? nm
-                          : std::max(1, std::min(std::max(nm / 16, 1), (1024 + S.n_tiles - 1) / S.n_tiles));
-    hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, parts), dim3(256), lds, st, d_inst, spin, Tin,
-                       grad_T, parts);
+    const bool split = (size_t)S.n_tiles * nm <= 65536;
+    const int parts = split ? (nm + GT_SPLIT_ENTRIES - 1) / GT_SPLIT_ENTRIES
+                            : std::max(1, std::min(std::max(nm / 16, 1), (1024 + S.n_tiles - 1) / S.n_tiles));
+    const int threads = split ? GT_SPLIT_THREADS : 256;
+    hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, parts), dim3(threads), lds, st, d_inst, spin, Tin,
+                       grad_T, parts, split ? 1 : 0);
     return hipGetLastError();
 }
 
