@@ -691,7 +691,7 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the walkers are "
               "independent, so a multi-GPU run would shard them with no per-move "
-              "communication; this build measures the one-GPU share.", file=sys.stderr)
+              "communication; bench.py measures the one-GPU share.", file=sys.stderr)
         sys.exit(2)
     rows_wanted = [x for x in args.rows.split(",") if x]
     for r in rows_wanted:

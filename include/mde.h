@@ -87,7 +87,7 @@ typedef enum {
                                    not (Sec. V); switch the reference
                                    (mde_set_reference) for this walker       */
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define MDE_MAX_ELEC  64        /* electrons per spin                         */
 #define MDE_MAX_VIRT  256       /* virtual orbitals per spin                  */
 #define MDE_MAX_ORDER 8         /* largest excitation order                   */
