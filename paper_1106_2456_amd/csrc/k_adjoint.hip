@@ -96,12 +96,11 @@ __device__ double cof_entry_generic(const double *tabs, const uint4 &ex, int k, 
     return y[l];
 }
 
-// table-gradient launch shape: with the lists split over a block's slots,
-// GT_SPLIT_ENTRIES consecutive entries per block (the tile's table staged
-// once for all of them) on GT_SPLIT_THREADS threads
+// table-gradient launch shape: GT_MAX_THREADS threads per block; with the
+// lists split over a block's slots, GT_SPLIT_ENTRIES consecutive entries per
+// block (the tile's table staged once for all of them)
 constexpr int GT_MAX_THREADS = 512;
 constexpr int GT_SPLIT_ENTRIES = 2;
-constexpr int GT_SPLIT_THREADS = 512;
 
 // grad_T_sigma: block (walker tile, part) stages the tile's table in LDS once
 // and takes the part's contiguous range of table entries.  In the split form
@@ -269,7 +268,7 @@ hipError_t launch_grad_T(hipStream_t st, const InstDev *d_inst, const InstDev &h
     const bool split = (size_t)S.n_tiles * nm <= 65536;
     const int parts = split ? (nm + GT_SPLIT_ENTRIES - 1) / GT_SPLIT_ENTRIES
                             : std::max(1, std::min(std::max(nm / 16, 1), (1024 + S.n_tiles - 1) / S.n_tiles));
-    const int threads = split ? GT_SPLIT_THREADS : 256;
+    const int threads = GT_MAX_THREADS;
     hipLaunchKernelGGL(k_grad_T, dim3(S.n_tiles, parts), dim3(threads), lds, st, d_inst, spin, Tin,
                        grad_T, parts, split ? 1 : 0);
     return hipGetLastError();
