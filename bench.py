@@ -46,7 +46,8 @@ PEAK_HBM_GBS = 8000.0
 
 # FP64 flops of one excitation of order k in the determinant kernel
 # (determinant, y = adj(S) c', four bordered derivative terms, five CI
-# accumulations); FMA counts 2.  See the design doc for the derivation.
+# accumulations), counted from the kernel's closed-form small determinants
+# of orders 1-4; FMA counts 2.
 DET_FLOPS = {1: 26, 2: 43, 3: 80, 4: 165}
 
 
