@@ -793,8 +793,11 @@ k_accept(const InstDev *__restrict__ insts, const MoveArgs *__restrict__ moves, 
     extern __shared__ double sha[];
     double *cp_s = sha;            // [n][WT]  c' = c / rho (0 for rejected walkers)
     double *rr_s = sha + n * WT;   // [n][WT]  a'^T A^-1 - e_i^T
-    if (tid < WT) acc_s[tid] = (tid < nw) ? (int)mv.accept[w0 + tid] : 0;
-    __syncthreads();
+    const int acc_me = (tid < WT && tid < nw) ? (int)mv.accept[w0 + tid] : 0;
+    if (tid < WT) acc_s[tid] = acc_me;
+    // a tile none of whose walkers accepted has nothing to commit (every
+    // write below is an accepted walker's); the whole block leaves together
+    if (!__syncthreads_or(acc_me)) return;
     {
         const auto cc = MDE_G(double, I.cc) + (size_t)t * n * WT;
         const auto rr = MDE_G(double, I.rrow) + (size_t)t * n * WT;
